@@ -1,0 +1,148 @@
+/*
+ * foveate.h -- C ABI of libfoveate.so, block-wise foveation on AMD MI355X
+ * (gfx950).
+ *
+ * The method (Malkin, Deza, Poggio, arXiv 2012.08655): a frame is cut into
+ * square fragments of side B; each fragment is blurred with one Gaussian whose
+ * strength follows the distance from the fragment midpoint to the fixation
+ * point (Sec. 2 "Block-wise Foveation", Fig. 1).  The Gaussian is Eq. (1)
+ * sampled at integer offsets, cut off beyond 3 sigma and normalised to sum 1
+ * (Appendix "Methods"); a foveal fragment is copied unchanged (Appendix
+ * "Workload of the Block").  Blurring is separable: a horizontal pass into an
+ * on-chip intermediate, then a vertical pass (Sec. 2, Alg. 1).
+ *
+ * Conventions used throughout:
+ *   - Coordinates are pixel-centre: (0,0) is the centre of the top-left pixel;
+ *     "image centre" of a w x h frame is ((w-1)/2, (h-1)/2).
+ *   - Fragment (bx, by) covers x in [origin_x + bx*B, origin_x + (bx+1)*B) and
+ *     y likewise, clipped to the frame; its midpoint is
+ *     (origin_x + bx*B + (B-1)/2, origin_y + by*B + (B-1)/2), also for
+ *     clipped edge fragments.
+ *   - sigma(e) = 0 when e < e0, else min(slope*(e - e0), cap); radius
+ *     r = ceil(3*sigma) in IEEE double; N = 2r+1 taps w_k = exp(-k^2/(2 sigma^2)),
+ *     normalised; a fragment with sigma = 0 is copied.
+ *   - Pixels beyond the frame edge take the value of the nearest edge pixel
+ *     (clamp-to-edge, per axis).
+ *   - u8 output: round half to even, clip to 0..255.  u8 input is convolved
+ *     in float32 on the raw 0..255 scale.
+ *
+ * Memory: the caller owns every pixel buffer (device memory).  The library
+ * never allocates or frees caller buffers.  forward/backward are asynchronous
+ * and ordered on the caller's HIP stream; they return once work is enqueued.
+ *
+ * Errors: every call returns a fov_status; 0 is success.  Calls never throw
+ * and never abort.  foveate_last_error() returns a thread-local description
+ * of the last non-OK status.
+ */
+#ifndef FOVEATE_H
+#define FOVEATE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FOV_OK = 0,
+    FOV_EINVAL = -1,    /* bad argument: null pointer, shape mismatch, bad parameter   */
+    FOV_EDTYPE = -2,    /* unsupported dtype or dtype pair                             */
+    FOV_ELAYOUT = -3,   /* negative strides or a self-overlapping output layout         */
+    FOV_EALIAS = -4,    /* output memory overlaps input memory                         */
+    FOV_ENOMEM = -5,    /* a library-internal device or pinned allocation failed       */
+    FOV_EAGAIN = -6,    /* server request table full; retry after polling             */
+    FOV_EHIP = -7,      /* a HIP runtime call failed; see foveate_last_error()         */
+    FOV_ECLOSED = -8,   /* server is shutting down                                     */
+    FOV_ENOTICKET = -9, /* unknown or already-retired ticket                           */
+    FOV_ERANGE = -10    /* a fragment radius exceeds what on-chip memory can hold      */
+} fov_status;
+
+typedef enum { FOV_U8 = 0, FOV_F32 = 1, FOV_F64 = 2 } fov_dtype;
+
+/*
+ * A strided 4-D view of device memory, logical dims (n, c, h, w) with
+ * element strides (not bytes).  HWC u8 frames and NCHW float tensors are both
+ * described by choosing strides: an n x h x w x 3 u8 batch has
+ * sn = h*w*3, sc = 1, sh = w*3, sw = 3.  Strides must be >= 0.
+ */
+typedef struct {
+    void* data;        /* device pointer; may be NULL only if the view is empty */
+    int32_t dtype;     /* fov_dtype */
+    int32_t n, c, h, w;
+    int64_t sn, sc, sh, sw;
+} fov_tensor;
+
+/* Per-frame foveation parameters (all distances in pixels). */
+typedef struct {
+    double fix_x, fix_y; /* fixation point, pixel-centre coordinates (finite)     */
+    double e0;           /* foveal radius: fragments nearer than e0 are copied      */
+    double slope;        /* sigma increase per px beyond e0 (>= 0)                  */
+    double cap;          /* largest sigma (>= 0)                                    */
+    int32_t block;       /* fragment side B, 1..64 (the paper's headline uses 32)   */
+    int32_t origin_x;    /* left edge of fragment column 0, in (-B, 0]; 0 = plain   */
+    int32_t origin_y;    /* top edge of fragment row 0, in (-B, 0]; 0 = plain       */
+    int32_t reserved;    /* must be 0                                               */
+    const float* sigma_map; /* optional device array [nby*nbx] (row-major) giving
+                               each fragment's sigma directly, in place of the
+                               ramp (Sec. 4: any image may define blur strength);
+                               values are clipped to [0, cap]; NaN counts as 0.
+                               NULL = use the ramp.                              */
+} fov_params;
+
+/*
+ * Fragment grid of an h x w frame under p: *nbx fragment columns, *nby rows.
+ * Host-only arithmetic, no device work.
+ */
+fov_status foveate_grid(int32_t h, int32_t w, const fov_params* p, int32_t* nbx, int32_t* nby);
+
+/*
+ * Per-fragment plan (Alg. 1 "grid of blurring strengths"), computed ON THE
+ * DEVICE by the same code the kernels run: sigma_out[by*nbx+bx] (double) and
+ * r_out[...] (int32), both device arrays of nby*nbx entries owned by the
+ * caller.  sigma_out may be NULL.  Asynchronous on `stream`.
+ */
+fov_status foveate_plan(int32_t h, int32_t w, const fov_params* p, double* sigma_out,
+                        int32_t* r_out, void* stream);
+
+/*
+ * Same plan computed on the host (used for launch sizing and cost ordering);
+ * host arrays of nby*nbx entries.  Not valid with a sigma_map (device data).
+ */
+fov_status foveate_plan_host(int32_t h, int32_t w, const fov_params* p, double* sigma_out,
+                             int32_t* r_out);
+
+/*
+ * Foveate n frames: out = A_p(in) (Sec. 2, Alg. 1 steps "place padded
+ * fragment into shared memory" .. "write result to output array").
+ *   in, out : same (n, c, h, w); dtype pairs u8->u8, u8->f32 (raw 0..255),
+ *             f32->f32, f64->f64.  out must not overlap in (FOV_EALIAS).
+ *   p       : np parameter sets, np == n (one per frame) or np == 1 (shared).
+ *   stream  : hipStream_t (NULL = default stream).
+ * Empty views (any extent 0) are a no-op.  Fails with FOV_ERANGE when a
+ * fragment's radius needs more on-chip memory than one workgroup may use.
+ */
+fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fov_params* p,
+                           int32_t np, void* stream);
+
+/*
+ * Adjoint (transpose) of foveate_forward for the same parameters:
+ * grad_in = A_p^T grad_out, computed as a gather (each workgroup owns a tile
+ * of grad_in and visits every fragment whose window reaches it; no atomics).
+ * Used as the backward pass of training through the foveation.  dtype pairs
+ * f32->f32 and f64->f64 only.  Same shape/alias/stream rules as forward.
+ */
+fov_status foveate_backward(const fov_tensor* grad_out, const fov_tensor* grad_in,
+                            const fov_params* p, int32_t np, void* stream);
+
+/* Thread-local message for the last non-OK status of this thread ("" if none). */
+const char* foveate_last_error(void);
+
+/* Library version string. */
+const char* foveate_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOVEATE_H */

@@ -1,0 +1,80 @@
+"""ctypes view of the C ABI in include/foveate.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfoveate.so")
+
+FOV_OK, FOV_EINVAL, FOV_EDTYPE, FOV_ELAYOUT, FOV_EALIAS = 0, -1, -2, -3, -4
+FOV_ENOMEM, FOV_EAGAIN, FOV_EHIP, FOV_ECLOSED, FOV_ENOTICKET, FOV_ERANGE = -5, -6, -7, -8, -9, -10
+STATUS_NAMES = {0: "FOV_OK", -1: "FOV_EINVAL", -2: "FOV_EDTYPE", -3: "FOV_ELAYOUT", -4: "FOV_EALIAS",
+                -5: "FOV_ENOMEM", -6: "FOV_EAGAIN", -7: "FOV_EHIP", -8: "FOV_ECLOSED",
+                -9: "FOV_ENOTICKET", -10: "FOV_ERANGE"}
+FOV_U8, FOV_F32, FOV_F64 = 0, 1, 2
+
+
+class FovTensor(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("c", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("sn", ctypes.c_int64), ("sc", ctypes.c_int64), ("sh", ctypes.c_int64), ("sw", ctypes.c_int64)]
+
+
+class FovParams(ctypes.Structure):
+    _fields_ = [("fix_x", ctypes.c_double), ("fix_y", ctypes.c_double), ("e0", ctypes.c_double),
+                ("slope", ctypes.c_double), ("cap", ctypes.c_double), ("block", ctypes.c_int32),
+                ("origin_x", ctypes.c_int32), ("origin_y", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sigma_map", ctypes.c_void_p)]
+
+
+# Every symbol declared in include/foveate.h, with (restype, argtypes).
+_TP = ctypes.POINTER(FovTensor)
+_PP = ctypes.POINTER(FovParams)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+SIGNATURES = {
+    "foveate_grid": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _PP, _I32P, _I32P]),
+    "foveate_plan": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _PP, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
+    "foveate_plan_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _PP, ctypes.c_void_p, ctypes.c_void_p]),
+    "foveate_forward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
+    "foveate_backward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
+    "foveate_last_error": (ctypes.c_char_p, []),
+    "foveate_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class FoveateError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+def lib():
+    """Load libfoveate.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfoveate.so is not built (run paper_2012_08655_amd._build.build()); "
+                              "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != FOV_OK:
+        raise FoveateError(status, lib().foveate_last_error().decode())
+    return status
+
+
+def make_params(p, sigma_map_ptr=None) -> FovParams:
+    return FovParams(float(p["fix_x"]), float(p["fix_y"]), float(p["e0"]), float(p["slope"]), float(p["cap"]),
+                     int(p.get("block", 32)), int(p.get("origin_x", 0)), int(p.get("origin_y", 0)), 0,
+                     sigma_map_ptr)

@@ -1,0 +1,157 @@
+"""Torch-facing binding of libfoveate.so.
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+computation runs in the library's HIP kernels.  Functions here only build the
+C descriptors (pointers, extents, element strides) and call the C ABI.
+
+Parameters are dicts with keys fix_x, fix_y, e0, slope, cap and optionally
+block (default 32), origin_x, origin_y (default 0) and sigma_map (a CUDA
+float32 tensor of nby*nbx per-fragment sigmas replacing the ramp).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Mapping, Sequence
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+_DTYPES = {torch.uint8: N.FOV_U8, torch.float32: N.FOV_F32, torch.float64: N.FOV_F64}
+LAYOUTS = ("NCHW", "NHWC", "CHW", "HWC", "HW")
+
+
+def _stream_handle(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def tensor_desc(t: torch.Tensor, layout: str) -> N.FovTensor:
+    """Describe a device tensor as (n, c, h, w) with element strides."""
+    if t.dtype not in _DTYPES:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    s = t.stride()
+    if layout == "NCHW":
+        n, c, h, w = t.shape
+        sn, sc, sh, sw = s
+    elif layout == "NHWC":
+        n, h, w, c = t.shape
+        sn, sh, sw, sc = s
+    elif layout == "CHW":
+        c, h, w = t.shape
+        n, (sc, sh, sw) = 1, s
+        sn = 0
+    elif layout == "HWC":
+        h, w, c = t.shape
+        n, (sh, sw, sc) = 1, s
+        sn = 0
+    elif layout == "HW":
+        h, w = t.shape
+        n, c, (sh, sw) = 1, 1, s
+        sn = sc = 0
+    else:
+        raise ValueError("layout must be one of %s" % (LAYOUTS,))
+    return N.FovTensor(t.data_ptr() if t.numel() else None, _DTYPES[t.dtype], n, c, h, w, sn, sc, sh, sw)
+
+
+def _params_array(params, n: int):
+    if isinstance(params, Mapping):
+        plist = [params]
+    else:
+        plist = list(params)
+        if len(plist) not in (1, n):
+            raise ValueError("need one params dict per frame (or one shared)")
+    arr = (N.FovParams * max(len(plist), 1))()
+    keep = []
+    for i, p in enumerate(plist):
+        sm = p.get("sigma_map")
+        ptr = None
+        if sm is not None:
+            if not (isinstance(sm, torch.Tensor) and sm.is_cuda and sm.dtype == torch.float32 and sm.is_contiguous()):
+                raise TypeError("sigma_map must be a contiguous CUDA float32 tensor")
+            ptr = sm.data_ptr()
+            keep.append(sm)
+        arr[i] = N.make_params(p, ptr)
+    return arr, len(plist), keep
+
+
+def _n_of(desc: N.FovTensor) -> int:
+    return desc.n
+
+
+def forward(x: torch.Tensor, params, out: torch.Tensor | None = None, layout: str = "NCHW",
+            out_dtype: torch.dtype | None = None, stream=None) -> torch.Tensor:
+    """Foveate ``x`` into ``out`` (allocated like ``x`` when None)."""
+    if out is None:
+        out = torch.empty_like(x, dtype=out_dtype or x.dtype)
+    di, do = tensor_desc(x, layout), tensor_desc(out, layout)
+    arr, npar, _keep = _params_array(params, di.n)
+    N.check(N.lib().foveate_forward(ctypes.byref(di), ctypes.byref(do), arr, npar, _stream_handle(stream)))
+    return out
+
+
+def backward(grad_out: torch.Tensor, params, grad_in: torch.Tensor | None = None, layout: str = "NCHW",
+             stream=None) -> torch.Tensor:
+    """grad_in = A^T grad_out for the same parameters as the forward."""
+    if grad_in is None:
+        grad_in = torch.empty_like(grad_out)
+    dg, di = tensor_desc(grad_out, layout), tensor_desc(grad_in, layout)
+    arr, npar, _keep = _params_array(params, dg.n)
+    N.check(N.lib().foveate_backward(ctypes.byref(dg), ctypes.byref(di), arr, npar, _stream_handle(stream)))
+    return grad_in
+
+
+def grid(h: int, w: int, params: Mapping) -> tuple[int, int]:
+    """(nby, nbx) fragment rows/columns of an h x w frame."""
+    p = N.make_params(params)
+    nbx, nby = ctypes.c_int32(), ctypes.c_int32()
+    N.check(N.lib().foveate_grid(h, w, ctypes.byref(p), ctypes.byref(nbx), ctypes.byref(nby)))
+    return nby.value, nbx.value
+
+
+def plan_device(h: int, w: int, params: Mapping, device="cuda"):
+    """Per-fragment (sigma f64, radius i32) computed by the device planner."""
+    nby, nbx = grid(h, w, params)
+    sig = torch.empty((nby, nbx), dtype=torch.float64, device=device)
+    rad = torch.empty((nby, nbx), dtype=torch.int32, device=device)
+    arr, _, _keep = _params_array(params, 1)
+    N.check(N.lib().foveate_plan(h, w, arr, ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(rad.data_ptr()),
+                                 _stream_handle()))
+    return sig, rad
+
+
+def plan_host(h: int, w: int, params: Mapping):
+    """Per-fragment (sigma, radius) computed by the host planner."""
+    nby, nbx = grid(h, w, params)
+    sig = np.zeros((nby, nbx), np.float64)
+    rad = np.zeros((nby, nbx), np.int32)
+    p = N.make_params(params)
+    N.check(N.lib().foveate_plan_host(h, w, ctypes.byref(p), ctypes.c_void_p(sig.ctypes.data),
+                                      ctypes.c_void_p(rad.ctypes.data)))
+    return sig, rad
+
+
+class FoveateFn(torch.autograd.Function):
+    """y = A_p x with the hand-written adjoint as its backward.  Gradients flow
+    to x only: sigma and r = ceil(3 sigma) are piecewise constant in the
+    parameters."""
+
+    @staticmethod
+    def forward(ctx, x, params, layout):
+        ctx.params = params
+        ctx.layout = layout
+        return forward(x, params, layout=layout)
+
+    @staticmethod
+    def backward(ctx, g):
+        g = g.contiguous()
+        return backward(g, ctx.params, layout=ctx.layout), None, None
+
+
+def foveate(x: torch.Tensor, params, layout: str = "NCHW") -> torch.Tensor:
+    """Differentiable foveation of a float tensor (f32 or f64)."""
+    return FoveateFn.apply(x, params, layout)

@@ -1,0 +1,294 @@
+// C ABI of libfoveate.so: argument validation, planning on the host for
+// launch sizing, and dispatch to the HIP kernels.  Every entry point returns a
+// fov_status and never throws.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "adjoint.h"
+#include "common.h"
+#include "forward.h"
+
+namespace fov {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct DeviceInfo {
+    bool ready = false;
+    size_t lds_limit = 0;  // dynamic LDS one workgroup may use
+    int cus = 0;
+};
+constexpr int kMaxDevices = 64;
+DeviceInfo g_dev[kMaxDevices];
+std::mutex g_dev_mu;
+
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+}  // namespace
+
+fov_status set_error(fov_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+fov_status hip_error(hipError_t e, const char* what) {
+    return set_error(FOV_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+fov_status device_info(const DeviceInfo** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return set_error(FOV_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceInfo& d = g_dev[dev];
+    if (!d.ready) {
+        int a = 0, b = 0, cus = 0;
+        e = hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return hip_error(e, "hipDeviceGetAttribute(shared per block)");
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            b = 0;
+        }
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_error(e, "hipDeviceGetAttribute(CU count)");
+        d.lds_limit = (size_t)std::max(a, b);
+        d.cus = cus;
+        d.ready = true;
+    }
+    *out = &d;
+    return FOV_OK;
+}
+
+namespace {
+
+size_t dtype_size(int dt) {
+    switch (dt) {
+        case FOV_U8: return 1;
+        case FOV_F32: return 4;
+        case FOV_F64: return 8;
+        default: return 0;
+    }
+}
+
+bool is_empty(const fov_tensor& t) { return t.n == 0 || t.c == 0 || t.h == 0 || t.w == 0; }
+
+// Largest element offset reachable in the view (strides >= 0).
+int64_t max_offset(const fov_tensor& t) {
+    return (int64_t)(t.n - 1) * t.sn + (int64_t)(t.c - 1) * t.sc + (int64_t)(t.h - 1) * t.sh +
+           (int64_t)(t.w - 1) * t.sw;
+}
+
+fov_status check_view(const fov_tensor* t, const char* name, bool is_output) {
+    if (!t) return set_error(FOV_EINVAL, std::string(name) + " is NULL");
+    if (t->n < 0 || t->c < 0 || t->h < 0 || t->w < 0) return set_error(FOV_EINVAL, std::string(name) + ": negative extent");
+    if (dtype_size(t->dtype) == 0) return set_error(FOV_EDTYPE, std::string(name) + ": unknown dtype");
+    if (is_empty(*t)) return FOV_OK;
+    if (!t->data) return set_error(FOV_EINVAL, std::string(name) + ": data is NULL");
+    if (t->sn < 0 || t->sc < 0 || t->sh < 0 || t->sw < 0)
+        return set_error(FOV_ELAYOUT, std::string(name) + ": negative stride");
+    if ((uintptr_t)t->data % dtype_size(t->dtype) != 0)
+        return set_error(FOV_ELAYOUT, std::string(name) + ": misaligned data pointer");
+    if (is_output) {
+        // Non-overlap: visiting dims by ascending stride, each stride must exceed
+        // the span of all smaller dims.
+        int64_t ext[4] = {t->n, t->c, t->h, t->w};
+        int64_t st[4] = {t->sn, t->sc, t->sh, t->sw};
+        int idx[4] = {0, 1, 2, 3};
+        std::sort(idx, idx + 4, [&](int a, int b) { return st[a] < st[b]; });
+        int64_t span = 0;
+        for (int k = 0; k < 4; ++k) {
+            int d = idx[k];
+            if (ext[d] == 1) continue;
+            if (st[d] <= span) return set_error(FOV_ELAYOUT, std::string(name) + ": layout overlaps itself");
+            span += (ext[d] - 1) * st[d];
+        }
+    }
+    if (max_offset(*t) > ((int64_t)1 << 40)) return set_error(FOV_EINVAL, std::string(name) + ": view too large");
+    return FOV_OK;
+}
+
+fov_status check_alias(const fov_tensor& a, const fov_tensor& b) {
+    uintptr_t a0 = (uintptr_t)a.data, a1 = a0 + (uintptr_t)(max_offset(a) + 1) * dtype_size(a.dtype);
+    uintptr_t b0 = (uintptr_t)b.data, b1 = b0 + (uintptr_t)(max_offset(b) + 1) * dtype_size(b.dtype);
+    if (a0 < b1 && b0 < a1) return set_error(FOV_EALIAS, "output memory overlaps input memory");
+    return FOV_OK;
+}
+
+fov_status check_params(const fov_params& p, int idx) {
+    auto bad = [&](const char* what) {
+        return set_error(FOV_EINVAL, "params[" + std::to_string(idx) + "]: " + what);
+    };
+    if (!std::isfinite(p.fix_x) || !std::isfinite(p.fix_y)) return bad("fixation must be finite");
+    if (!std::isfinite(p.e0)) return bad("e0 must be finite");
+    if (!std::isfinite(p.slope) || p.slope < 0) return bad("slope must be finite and >= 0");
+    if (!std::isfinite(p.cap) || p.cap < 0) return bad("cap must be finite and >= 0");
+    if (p.block < 1 || p.block > kMaxBlock) return bad("block must be in 1..64");
+    if (p.origin_x > 0 || p.origin_x <= -p.block || p.origin_y > 0 || p.origin_y <= -p.block)
+        return bad("origin must lie in (-block, 0]");
+    if (p.reserved != 0) return bad("reserved must be 0");
+    return FOV_OK;
+}
+
+FrameParams to_frame(const fov_params& p, int h, int w) {
+    FrameParams f;
+    f.fix_x = p.fix_x; f.fix_y = p.fix_y; f.e0 = p.e0; f.slope = p.slope; f.cap = p.cap;
+    f.block = p.block; f.origin_x = p.origin_x; f.origin_y = p.origin_y;
+    f.nbx = grid_extent(w, p.origin_x, p.block);
+    f.sigma_map = p.sigma_map;
+    (void)h;
+    return f;
+}
+
+// Largest fragment radius of a frame.  For the eccentricity ramp, distance to
+// the fixation is convex over the fragment grid, so its maximum (and hence the
+// largest sigma) is reached at one of the four corner fragments.  With a sigma
+// map the bound is the cap.
+int frame_r_max(const FrameParams& f, int h) {
+    if (f.sigma_map) return radius_of(f.cap);
+    int nby = grid_extent(h, f.origin_y, f.block);
+    int r = 0;
+    const int xs[2] = {0, f.nbx - 1}, ys[2] = {0, nby - 1};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) r = std::max(r, radius_of(fragment_sigma_ramp(f, xs[i], ys[j])));
+    return r;
+}
+
+int strip_rows_setting() {
+    static int v = std::max(1, env_int("FOV_STRIP_ROWS", 32));
+    return v;
+}
+
+}  // namespace
+}  // namespace fov
+
+using namespace fov;
+
+extern "C" {
+
+const char* foveate_last_error(void) { return g_last_error.c_str(); }
+
+const char* foveate_version(void) { return "libfoveate 0.1 (gfx950)"; }
+
+fov_status foveate_grid(int32_t h, int32_t w, const fov_params* p, int32_t* nbx, int32_t* nby) {
+    if (!p || !nbx || !nby) return set_error(FOV_EINVAL, "NULL argument");
+    if (h < 1 || w < 1) return set_error(FOV_EINVAL, "frame must be at least 1x1");
+    fov_status s = check_params(*p, 0);
+    if (s != FOV_OK) return s;
+    *nbx = grid_extent(w, p->origin_x, p->block);
+    *nby = grid_extent(h, p->origin_y, p->block);
+    return FOV_OK;
+}
+
+fov_status foveate_plan_host(int32_t h, int32_t w, const fov_params* p, double* sigma_out, int32_t* r_out) {
+    int32_t nbx, nby;
+    fov_status s = foveate_grid(h, w, p, &nbx, &nby);
+    if (s != FOV_OK) return s;
+    if (!r_out) return set_error(FOV_EINVAL, "r_out is NULL");
+    if (p->sigma_map) return set_error(FOV_EINVAL, "host plan cannot read a device sigma map");
+    FrameParams f = to_frame(*p, h, w);
+    for (int by = 0; by < nby; ++by)
+        for (int bx = 0; bx < nbx; ++bx) {
+            double sg = fragment_sigma_ramp(f, bx, by);
+            if (sigma_out) sigma_out[by * nbx + bx] = sg;
+            r_out[by * nbx + bx] = radius_of(sg);
+        }
+    return FOV_OK;
+}
+
+fov_status foveate_plan(int32_t h, int32_t w, const fov_params* p, double* sigma_out, int32_t* r_out, void* stream) {
+    int32_t nbx, nby;
+    fov_status s = foveate_grid(h, w, p, &nbx, &nby);
+    if (s != FOV_OK) return s;
+    if (!r_out) return set_error(FOV_EINVAL, "r_out is NULL");
+    return launch_plan(to_frame(*p, h, w), nbx * nby, sigma_out, r_out, (hipStream_t)stream);
+}
+
+// Shared validation of forward/backward arguments; fills frames[] and r_max.
+static fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
+                          bool backward, bool* empty) {
+    fov_status s;
+    if ((s = check_view(in, backward ? "grad_out" : "in", false)) != FOV_OK) return s;
+    if ((s = check_view(out, backward ? "grad_in" : "out", true)) != FOV_OK) return s;
+    if (in->n != out->n || in->c != out->c || in->h != out->h || in->w != out->w)
+        return set_error(FOV_EINVAL, "input and output shapes differ");
+    if (backward) {
+        if (!((in->dtype == FOV_F32 && out->dtype == FOV_F32) || (in->dtype == FOV_F64 && out->dtype == FOV_F64)))
+            return set_error(FOV_EDTYPE, "backward supports f32->f32 and f64->f64");
+    } else {
+        bool ok = (in->dtype == FOV_U8 && (out->dtype == FOV_U8 || out->dtype == FOV_F32)) ||
+                  (in->dtype == FOV_F32 && out->dtype == FOV_F32) || (in->dtype == FOV_F64 && out->dtype == FOV_F64);
+        if (!ok) return set_error(FOV_EDTYPE, "unsupported dtype pair");
+    }
+    *empty = is_empty(*in);
+    if (*empty) return FOV_OK;
+    if ((s = check_alias(*in, *out)) != FOV_OK) return s;
+    if (!p) return set_error(FOV_EINVAL, "params is NULL");
+    if (np != in->n && np != 1) return set_error(FOV_EINVAL, "np must equal n or 1");
+    for (int i = 0; i < np; ++i)
+        if ((s = check_params(p[i], i)) != FOV_OK) return s;
+    return FOV_OK;
+}
+
+fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
+                           void* stream) {
+    bool empty = false;
+    fov_status s = prepare(in, out, p, np, false, &empty);
+    if (s != FOV_OK || empty) return s;
+    const DeviceInfo* dev = nullptr;
+    if ((s = device_info(&dev)) != FOV_OK) return s;
+    const int es = in->dtype == FOV_F64 ? 8 : 4;
+    const int sr = strip_rows_setting();
+
+    for (int f0 = 0; f0 < in->n; f0 += kMaxFramesPerLaunch) {
+        const int nf = std::min(kMaxFramesPerLaunch, in->n - f0);
+        FwdLaunch a;
+        std::memset(&a, 0, sizeof(a));
+        a.in = View{in->data, in->sn, in->sc, in->sh, in->sw};
+        a.out = View{out->data, out->sn, out->sc, out->sh, out->sw};
+        a.c = in->c; a.h = in->h; a.w = in->w;
+        a.nframes = nf;
+        a.frame_base = f0;
+        a.strip_rows = sr;
+        int r_cap = 0, bmax = 1, total = 0;
+        for (int i = 0; i < nf; ++i) {
+            const fov_params& pp = p[np == 1 ? 0 : f0 + i];
+            a.fr[i] = to_frame(pp, in->h, in->w);
+            a.blk_prefix[i] = total;
+            total += a.fr[i].nbx * grid_extent(in->h, pp.origin_y, pp.block);
+            r_cap = std::max(r_cap, frame_r_max(a.fr[i], in->h));
+            bmax = std::max(bmax, pp.block);
+        }
+        a.blk_prefix[nf] = total;
+        a.r_cap = r_cap;
+        size_t lds = r_cap > 0 ? lds_bytes(r_cap, bmax, es, sr) : 64;
+        if (lds > dev->lds_limit)
+            return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
+                                             " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
+        if ((s = launch_forward(a, total, in->dtype, out->dtype, lds, (hipStream_t)stream, dev->lds_limit)) != FOV_OK)
+            return s;
+    }
+    return FOV_OK;
+}
+
+fov_status foveate_backward(const fov_tensor* grad_out, const fov_tensor* grad_in, const fov_params* p, int32_t np,
+                            void* stream) {
+    bool empty = false;
+    fov_status s = prepare(grad_out, grad_in, p, np, true, &empty);
+    if (s != FOV_OK || empty) return s;
+    const DeviceInfo* dev = nullptr;
+    if ((s = device_info(&dev)) != FOV_OK) return s;
+    return launch_adjoint_all(grad_out, grad_in, p, np, (hipStream_t)stream, dev->lds_limit);
+}
+
+}  // extern "C"

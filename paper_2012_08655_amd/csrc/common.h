@@ -1,0 +1,113 @@
+// Internal definitions shared by the HIP sources of libfoveate.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/foveate.h"
+
+namespace fov {
+
+// Frames whose parameters travel in one launch's kernel arguments.
+constexpr int kMaxFramesPerLaunch = 32;
+// Largest fragment side the kernels accept.
+constexpr int kMaxBlock = 64;
+// Threads per workgroup of the per-fragment kernels (four wave64s).
+constexpr int kThreads = 256;
+
+// One frame's parameters as the device sees them.
+struct FrameParams {
+    double fix_x, fix_y, e0, slope, cap;
+    int32_t block, origin_x, origin_y, nbx;
+    const float* sigma_map;
+};
+
+// Fragment grid of an h x w frame: columns/rows covering it for a grid whose
+// fragment (0,0) starts at (origin_x, origin_y), origin in (-B, 0].
+__host__ __device__ inline int grid_extent(int len, int origin, int B) {
+    // number of fragments covering [0, len): ceil((len - origin) / B)
+    return (len - origin + B - 1) / B;
+}
+
+// Blur strength of fragment (bx, by) (Sec. 2: each fragment is blurred
+// according to the distance from its midpoint to the fixation point).
+// Midpoint in pixel-centre coordinates; sigma(e) = 0 below e0, else
+// min(slope*(e - e0), cap).  IEEE double with no contraction so the host and
+// the device produce the same bits; sqrt is correctly rounded on both.
+__host__ __device__ inline double fragment_sigma_ramp(const FrameParams& f, int bx, int by) {
+#pragma clang fp contract(off)
+    double half = (double)(f.block - 1) / 2.0;
+    double cx = (double)f.origin_x + (double)bx * (double)f.block + half;
+    double cy = (double)f.origin_y + (double)by * (double)f.block + half;
+    double dx = cx - f.fix_x;
+    double dy = cy - f.fix_y;
+    double e = sqrt(dx * dx + dy * dy);
+    if (e < f.e0) return 0.0;
+    double s = f.slope * (e - f.e0);
+    if (s > f.cap) s = f.cap;
+    return s > 0.0 ? s : 0.0;
+}
+
+// A sigma-map entry clipped to [0, cap]; NaN and negatives mean "copy".
+__host__ __device__ inline double clip_map_sigma(double m, double cap) {
+    if (!(m > 0.0)) return 0.0;
+    double s = m < cap ? m : cap;
+    return s > 0.0 ? s : 0.0;
+}
+
+// Window radius: taps beyond 3 sigma are dropped (Appendix "Methods").
+__host__ __device__ inline int radius_of(double sigma) {
+    if (!(sigma > 0.0)) return 0;
+    return (int)ceil(3.0 * sigma);
+}
+
+// Workgroup-tile geometry of one fragment pass, shared by the host (LDS
+// sizing) and the device (LDS carving).  Taps are padded with zero weights to
+// a multiple of 8 (NP); the horizontal pass computes 8 outputs per thread and
+// the vertical pass 4, each sliding an 8-tap window through registers.
+struct TileGeom {
+    int NP;   // padded tap count
+    int TH;   // intermediate rows (fragment rows + halo + window overrun)
+    int TW;   // staged tile columns
+    int TP;   // staged tile row pitch (elements)
+    int IP;   // intermediate row pitch (elements)
+};
+
+constexpr int kPH = 8;  // outputs per thread, horizontal pass
+constexpr int kPV = 4;  // outputs per thread, vertical pass
+constexpr int kU = 8;   // taps per register-window step
+
+__host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+__host__ __device__ inline TileGeom tile_geom(int r, int bw, int bh) {
+    TileGeom g;
+    g.NP = round_up(2 * r + 1, kU);
+    g.TW = round_up(bw, kPH) + g.NP;
+    g.TH = round_up(bh, kPV) - kPV + g.NP + kU;
+    g.TP = round_up(g.TW, 4) + 4;
+    g.IP = round_up(bw, kPH) + 4;
+    return g;
+}
+
+// LDS bytes one workgroup needs for radius r, fragment side B, element size
+// es, staging strip height sr (rows of the input tile resident at once).
+__host__ __device__ inline size_t lds_bytes(int r, int B, int es, int sr) {
+    TileGeom g = tile_geom(r, B, B);
+    int rows = sr < g.TH ? sr : g.TH;
+    size_t wts = (size_t)round_up(g.NP, 4) * es;
+    return wts + (size_t)rows * g.TP * es + (size_t)g.TH * g.IP * es + 64;
+}
+
+// Strided 4-D view as the kernels see it.
+struct View {
+    void* data;
+    int64_t sn, sc, sh, sw;
+};
+
+// Thread-local error reporting.
+fov_status set_error(fov_status s, const std::string& msg);
+fov_status hip_error(hipError_t e, const char* what);
+
+}  // namespace fov

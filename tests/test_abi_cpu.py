@@ -1,0 +1,134 @@
+"""Host-side checks of libfoveate.so: exports, host planner, argument
+validation.  No kernel runs here (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2012_08655_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "foveate.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(foveate_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_header_symbol():
+    lib = N.lib()
+    names = header_functions()
+    assert "foveate_forward" in names and "foveate_backward" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in N.SIGNATURES, "binding lacks " + name
+
+
+def test_version_and_error_strings():
+    lib = N.lib()
+    assert b"gfx950" in lib.foveate_version()
+    assert isinstance(lib.foveate_last_error(), bytes)
+
+
+def test_grid_matches_oracle(orc):
+    lib = N.lib()
+    for (h, w, B, ox, oy) in [(256, 256, 32, 0, 0), (1080, 1920, 32, 0, 0), (70, 90, 32, -5, -11),
+                              (1, 1, 1, 0, 0), (33, 31, 16, -15, 0)]:
+        p = synth.params_dict(0, 0, 0, 0, 0, B, ox, oy)
+        nbx, nby = ctypes.c_int32(), ctypes.c_int32()
+        assert lib.foveate_grid(h, w, ctypes.byref(N.make_params(p)), ctypes.byref(nbx), ctypes.byref(nby)) == 0
+        assert (nby.value, nbx.value) == orc.grid(h, w, p)
+
+
+def host_plan(h, w, p):
+    from paper_2012_08655_amd import api
+    return api.plan_host(h, w, p)
+
+
+def test_host_plan_bit_identical_to_oracle(orc):
+    # Same reading of the ramp, evaluated independently: sigma must agree to
+    # the bit and r exactly (r = ceil(3 sigma) is discontinuous).
+    rng = np.random.default_rng(11)
+    cases = [(256, 256, synth.params_cfg1()), (1080, 1920, synth.params_cfg2(centred=True))]
+    for _ in range(40):
+        h, w = int(rng.integers(1, 900)), int(rng.integers(1, 900))
+        B = int(rng.choice([1, 7, 16, 32, 64]))
+        cases.append((h, w, synth.params_dict(rng.uniform(-50, w + 50), rng.uniform(-50, h + 50),
+                                              rng.uniform(-10, 100), rng.uniform(0, 0.3), rng.uniform(0, 25), B,
+                                              -int(rng.integers(0, B)), -int(rng.integers(0, B)))))
+    for h, w, p in cases:
+        s_o, r_o = orc.plan(h, w, p)
+        s_h, r_h = host_plan(h, w, p)
+        assert np.array_equal(r_o, r_h)
+        assert np.array_equal(s_o.view(np.int64), s_h.view(np.int64))
+
+
+def fake_desc(dtype, n, c, h, w, ptr=0x10000000, layout="NCHW"):
+    if layout == "NCHW":
+        st = (c * h * w, h * w, w, 1)
+    else:
+        st = (h * w * c, 1, w * c, c)
+    return N.FovTensor(ptr, dtype, n, c, h, w, *st)
+
+
+def call_fwd(di, do, p, np_=1):
+    arr = (N.FovParams * 1)(N.make_params(p))
+    return N.lib().foveate_forward(ctypes.byref(di), ctypes.byref(do), arr, np_, None)
+
+
+P0 = synth.params_dict(10, 10, 5, 0.1, 4)
+
+
+def test_validation_errors_before_any_device_work():
+    L = N.lib()
+    a = fake_desc(N.FOV_F32, 1, 3, 64, 64, 0x10000000)
+    b = fake_desc(N.FOV_F32, 1, 3, 64, 64, 0x20000000)
+    arr = (N.FovParams * 1)(N.make_params(P0))
+    assert L.foveate_forward(None, ctypes.byref(b), arr, 1, None) == N.FOV_EINVAL
+    assert L.foveate_forward(ctypes.byref(a), ctypes.byref(b), None, 1, None) == N.FOV_EINVAL
+    # dtype pairs
+    assert call_fwd(fake_desc(N.FOV_F32, 1, 3, 64, 64), fake_desc(N.FOV_U8, 1, 3, 64, 64, 0x20000000), P0) == N.FOV_EDTYPE
+    assert call_fwd(fake_desc(7, 1, 3, 64, 64), b, P0) == N.FOV_EDTYPE
+    # shapes
+    assert call_fwd(a, fake_desc(N.FOV_F32, 1, 3, 64, 63, 0x20000000), P0) == N.FOV_EINVAL
+    # aliasing: overlapping ranges
+    assert call_fwd(a, fake_desc(N.FOV_F32, 1, 3, 64, 64, 0x10000000 + 4096), P0) == N.FOV_EALIAS
+    # negative stride
+    bad = fake_desc(N.FOV_F32, 1, 3, 64, 64, 0x20000000)
+    bad.sw = -1
+    assert call_fwd(a, bad, P0) == N.FOV_ELAYOUT
+    # self-overlapping output
+    ov = fake_desc(N.FOV_F32, 1, 3, 64, 64, 0x20000000)
+    ov.sc = 1
+    assert call_fwd(a, ov, P0) == N.FOV_ELAYOUT
+    # parameters
+    for key, val in [("slope", -1.0), ("cap", float("nan")), ("fix_x", float("inf")), ("block", 0),
+                     ("block", 65), ("origin_x", 1), ("origin_y", -32)]:
+        p = dict(P0)
+        p[key] = val
+        assert call_fwd(a, b, p) == N.FOV_EINVAL, key
+    msg = L.foveate_last_error().decode()
+    assert "origin" in msg
+    # np must be n or 1
+    a2 = fake_desc(N.FOV_F32, 2, 3, 64, 64, 0x10000000)
+    b2 = fake_desc(N.FOV_F32, 2, 3, 64, 64, 0x20000000)
+    arr3 = (N.FovParams * 3)(*(N.make_params(P0) for _ in range(3)))
+    assert L.foveate_forward(ctypes.byref(a2), ctypes.byref(b2), arr3, 3, None) == N.FOV_EINVAL
+
+
+def test_empty_views_are_noops():
+    for dims in [(0, 3, 8, 8), (2, 0, 8, 8), (2, 3, 0, 8), (2, 3, 8, 0)]:
+        a = N.FovTensor(None, N.FOV_F32, *dims, 0, 0, 0, 0)
+        b = N.FovTensor(None, N.FOV_F32, *dims, 0, 0, 0, 0)
+        assert call_fwd(a, b, P0) == N.FOV_OK
+
+
+def test_backward_rejects_u8():
+    a = fake_desc(N.FOV_U8, 1, 3, 8, 8, 0x10000000)
+    b = fake_desc(N.FOV_U8, 1, 3, 8, 8, 0x20000000)
+    arr = (N.FovParams * 1)(N.make_params(P0))
+    assert N.lib().foveate_backward(ctypes.byref(a), ctypes.byref(b), arr, 1, None) == N.FOV_EDTYPE
