@@ -8,8 +8,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 
 #include "adjoint.h"
 #include "common.h"
@@ -72,6 +74,43 @@ fov_status device_info(const DeviceInfo** out) {
 
 namespace {
 
+// Library-owned device workspace, one per (device, stream): work queued on one
+// stream is ordered, so consecutive calls on that stream may reuse it.  It
+// only grows; before freeing a smaller one the stream is drained.
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+fov_status workspace(hipStream_t stream, size_t bytes, void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace& w = g_ws[{dev, stream}];
+    if (w.bytes < bytes) {
+        if (w.ptr) {
+            e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize(workspace growth)");
+            e = hipFree(w.ptr);
+            if (e != hipSuccess) return hip_error(e, "hipFree(workspace)");
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        size_t nb = std::max(bytes, (size_t)1 << 20);
+        e = hipMalloc(&w.ptr, nb);
+        if (e != hipSuccess) {
+            w.ptr = nullptr;
+            return set_error(FOV_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+        }
+        w.bytes = nb;
+    }
+    *out = w.ptr;
+    return FOV_OK;
+}
+
 size_t dtype_size(int dt) {
     switch (dt) {
         case FOV_U8: return 1;
@@ -115,6 +154,8 @@ fov_status check_view(const fov_tensor* t, const char* name, bool is_output) {
         }
     }
     if (max_offset(*t) > ((int64_t)1 << 40)) return set_error(FOV_EINVAL, std::string(name) + ": view too large");
+    if ((int64_t)(t->w - 1) * t->sw >= ((int64_t)1 << 31))
+        return set_error(FOV_EINVAL, std::string(name) + ": a row spans more than 2^31 elements");
     return FOV_OK;
 }
 
@@ -164,9 +205,23 @@ int frame_r_max(const FrameParams& f, int h) {
     return r;
 }
 
-int strip_rows_setting() {
-    static int v = std::max(1, env_int("FOV_STRIP_ROWS", 32));
-    return v;
+// Padded-tile rows resident in LDS at once.  FOV_STRIP_ROWS forces a value;
+// otherwise the whole tile when it fits the per-workgroup LDS target (so that
+// several workgroups share a CU), else the tallest multiple of 8 rows that
+// does, else the tallest that fits the device limit at all.
+int choose_strip_rows(int in_dtype, int r_cap, int B, size_t lds_limit) {
+    static const int forced = env_int("FOV_STRIP_ROWS", 0);
+    if (forced > 0) return forced;
+    static const size_t target = (size_t)std::max(16, env_int("FOV_LDS_TARGET_KB", 64)) * 1024;
+    const int full = 1 << 20;
+    if (forward_lds_bytes(in_dtype, r_cap, B, full) <= target) return full;
+    for (size_t lim : {target, lds_limit}) {
+        int best = 0;
+        for (int sr = 8; sr <= 512; sr += 8)
+            if (forward_lds_bytes(in_dtype, r_cap, B, sr) <= lim) best = sr;
+        if (best > 0) return best;
+    }
+    return 8;
 }
 
 }  // namespace
@@ -247,8 +302,7 @@ fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fo
     if (s != FOV_OK || empty) return s;
     const DeviceInfo* dev = nullptr;
     if ((s = device_info(&dev)) != FOV_OK) return s;
-    const int es = in->dtype == FOV_F64 ? 8 : 4;
-    const int sr = strip_rows_setting();
+    const int wsize = in->dtype == FOV_F64 ? 8 : 4;
 
     for (int f0 = 0; f0 < in->n; f0 += kMaxFramesPerLaunch) {
         const int nf = std::min(kMaxFramesPerLaunch, in->n - f0);
@@ -259,7 +313,6 @@ fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fo
         a.c = in->c; a.h = in->h; a.w = in->w;
         a.nframes = nf;
         a.frame_base = f0;
-        a.strip_rows = sr;
         int r_cap = 0, bmax = 1, total = 0;
         for (int i = 0; i < nf; ++i) {
             const fov_params& pp = p[np == 1 ? 0 : f0 + i];
@@ -271,11 +324,18 @@ fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fo
         }
         a.blk_prefix[nf] = total;
         a.r_cap = r_cap;
-        size_t lds = r_cap > 0 ? lds_bytes(r_cap, bmax, es, sr) : 64;
+        a.wstride = round_up(2 * r_cap + 1, 16);
+        const int sr = choose_strip_rows(in->dtype, r_cap, bmax, dev->lds_limit);
+        a.strip_rows = sr;
+        const size_t lds = forward_lds_bytes(in->dtype, r_cap, bmax, sr);
         if (lds > dev->lds_limit)
             return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
                                              " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
-        if ((s = launch_forward(a, total, in->dtype, out->dtype, lds, (hipStream_t)stream, dev->lds_limit)) != FOV_OK)
+        void* ws = nullptr;
+        if ((s = workspace((hipStream_t)stream, plan_bytes(total, a.wstride, wsize), &ws)) != FOV_OK) return s;
+        const PlanBuffers plan = carve_plan(ws, total);
+        if ((s = launch_forward(a, total, in->dtype, out->dtype, lds, plan, (hipStream_t)stream, dev->lds_limit)) !=
+            FOV_OK)
             return s;
     }
     return FOV_OK;

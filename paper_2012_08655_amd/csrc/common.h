@@ -63,42 +63,7 @@ __host__ __device__ inline int radius_of(double sigma) {
     return (int)ceil(3.0 * sigma);
 }
 
-// Workgroup-tile geometry of one fragment pass, shared by the host (LDS
-// sizing) and the device (LDS carving).  Taps are padded with zero weights to
-// a multiple of 8 (NP); the horizontal pass computes 8 outputs per thread and
-// the vertical pass 4, each sliding an 8-tap window through registers.
-struct TileGeom {
-    int NP;   // padded tap count
-    int TH;   // intermediate rows (fragment rows + halo + window overrun)
-    int TW;   // staged tile columns
-    int TP;   // staged tile row pitch (elements)
-    int IP;   // intermediate row pitch (elements)
-};
-
-constexpr int kPH = 8;  // outputs per thread, horizontal pass
-constexpr int kPV = 4;  // outputs per thread, vertical pass
-constexpr int kU = 8;   // taps per register-window step
-
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
-
-__host__ __device__ inline TileGeom tile_geom(int r, int bw, int bh) {
-    TileGeom g;
-    g.NP = round_up(2 * r + 1, kU);
-    g.TW = round_up(bw, kPH) + g.NP;
-    g.TH = round_up(bh, kPV) - kPV + g.NP + kU;
-    g.TP = round_up(g.TW, 4) + 4;
-    g.IP = round_up(bw, kPH) + 4;
-    return g;
-}
-
-// LDS bytes one workgroup needs for radius r, fragment side B, element size
-// es, staging strip height sr (rows of the input tile resident at once).
-__host__ __device__ inline size_t lds_bytes(int r, int B, int es, int sr) {
-    TileGeom g = tile_geom(r, B, B);
-    int rows = sr < g.TH ? sr : g.TH;
-    size_t wts = (size_t)round_up(g.NP, 4) * es;
-    return wts + (size_t)rows * g.TP * es + (size_t)g.TH * g.IP * es + 64;
-}
 
 // Strided 4-D view as the kernels see it.
 struct View {
