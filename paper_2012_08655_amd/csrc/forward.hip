@@ -1,14 +1,17 @@
 // Forward block-wise foveation for gfx950.
 //
-// Two launches per batch of frames on the caller's stream:
+// Three launches per batch of frames on the caller's stream:
 //
 //  1. fov_plan_kernel — one wavefront per fragment: the fragment's sigma from
 //     its midpoint's eccentricity (Sec. 2, Fig. 1), radius r = ceil(3 sigma)
 //     and the normalised taps w_k = exp(-k^2/(2 sigma^2)) / sum (Eq. 1 cut at
 //     3 sigma, Appendix "Methods"), summed with wavefront shuffles, written to
-//     the plan workspace zero-padded to a multiple of 4 taps.
+//     the plan workspace.
 //
-//  2. fov_fwd_kernel — one workgroup per output fragment (Alg. 1): the padded
+//  2. fov_order_kernel — a counting sort of fragments by decreasing radius,
+//     the dispatch order of the main kernel (costliest fragments first).
+//
+//  3. fov_fwd_kernel — one workgroup per output fragment (Alg. 1): the padded
 //     tile (fragment plus r on each side, clamp-to-edge) is staged into LDS
 //     with row-coalesced loads, 8-bit input kept exact as fp16; a horizontal
 //     pass writes the fp32 intermediate into LDS; a vertical pass produces the
@@ -36,40 +39,55 @@ constexpr int kPV = 4;  // outputs per thread, vertical pass
 constexpr int kU = 4;   // taps per register-window step
 
 struct Geom {
-    int NP;  // taps padded to a multiple of kU (padding taps have weight 0)
+    int N;   // taps, 2r+1
     int G;   // horizontal-pass column groups
     int GV;  // vertical-pass row groups
-    int TW;  // staged tile columns
-    int TH;  // staged tile rows = intermediate rows
+    int TW;  // staged tile columns (8G + 2r)
+    int TH;  // staged tile rows = intermediate rows (4GV + 2r)
 };
 
 __host__ __device__ inline Geom geom(int r, int bw, int bh) {
     Geom g;
-    g.NP = round_up(2 * r + 1, kU);
+    g.N = 2 * r + 1;
     g.G = (bw + kPH - 1) / kPH;
     g.GV = (bh + kPV - 1) / kPV;
-    g.TW = g.G * kPH + g.NP;
-    g.TH = g.GV * kPV + g.NP;
+    g.TW = g.G * kPH + g.N - 1;
+    g.TH = g.GV * kPV + g.N - 1;
     return g;
 }
 
-// Tile row pitch in elements: rows start 16 bytes apart modulo 128 bytes, so
-// eight lanes reading 16 bytes from eight consecutive rows hit 32 distinct
-// LDS banks.
+// Window loads run up to 3 elements past the last staged column and 4 rows
+// past the last intermediate row (values that no tap uses); the pitch and the
+// allocation leave room for them.
+constexpr int kColSlack = 4;
+constexpr int kRowSlack = 4;
+
+// Tile row pitch in elements.  A horizontal-pass lane reads 4 elements (4*es
+// bytes) per load from its own row, and the lanes of a group sit on
+// consecutive rows; rows start 4*es bytes apart modulo 128 so that 128/(4*es)
+// such lanes cover the 32 LDS banks once.
 __host__ __device__ inline int tile_pitch(int TW, int es) {
-    const int q = 16 / es, m = 128 / es;
-    return round_up(TW > q ? TW - q : 1, m) + q;
+    const int q = 4, m = 128 / es;
+    const int need = TW + kColSlack;
+    return round_up(need > q ? need - q : 1, m) + q;
 }
 
-__host__ __device__ inline int inter_pitch(int bmax) { return bmax + 4; }
+// The intermediate is stored column-major (one column of TH rows after
+// another) so the vertical pass reads four rows with one 16-byte load.  Column
+// pitch in elements: columns start 16 bytes apart modulo 128 bytes (eight
+// lanes on eight consecutive columns hit 32 distinct banks), with room for
+// the window's overrun past the last row.
+__host__ __device__ inline int inter_pitch(int TH, int es) {
+    const int q = 16 / es, m = 128 / es;
+    const int need = TH + kRowSlack;
+    return round_up(need > q ? need - q : 1, m) + q;
+}
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 // ---- element conversions ----------------------------------------------------------------------
 template <typename TS, typename TIn>
 __device__ __forceinline__ TS to_stage(TIn v) { return (TS)v; }
-template <>
-__device__ __forceinline__ _Float16 to_stage<_Float16, uint8_t>(uint8_t v) { return (_Float16)(uint16_t)v; }
 
 template <typename TOut, typename TC>
 __device__ __forceinline__ TOut to_out(TC v) { return (TOut)v; }
@@ -84,6 +102,9 @@ template <typename TOut, typename TIn>
 __device__ __forceinline__ TOut copy_out(TIn v) { return (TOut)v; }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Index of the calling wavefront in its workgroup, as a scalar (uniform) value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // ---- LDS window loads -------------------------------------------------------------------------
 template <typename T>
@@ -109,12 +130,12 @@ __device__ __forceinline__ void load4_col(const T* p, T (&b)[4]) {
     for (int k = 0; k < 4; ++k) b[k] = p[k * IP];
 }
 
-// Horizontal step: taps j0..j0+3 on 8 outputs; window = X ++ Y ++ Z[0..2].
-template <typename TC, typename TS>
+// Horizontal step: taps j0..j0+NT-1 on 8 outputs; window = X ++ Y ++ Z[0..2].
+template <int NT = kU, typename TC, typename TS>
 __device__ __forceinline__ void hstep(TC (&acc)[kPH], const TS (&X)[4], const TS (&Y)[4], const TS (&Z)[4],
                                       const TC* __restrict__ w) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < NT; ++u) {
         const TC wu = w[u];
 #pragma unroll
         for (int p = 0; p < kPH; ++p) {
@@ -125,11 +146,11 @@ __device__ __forceinline__ void hstep(TC (&acc)[kPH], const TS (&X)[4], const TS
     }
 }
 
-// Vertical step: taps j0..j0+3 on 4 outputs; window = X ++ Y[0..2].
-template <typename TC>
+// Vertical step: taps j0..j0+NT-1 on 4 outputs; window = X ++ Y[0..2].
+template <int NT = kU, typename TC>
 __device__ __forceinline__ void vstep(TC (&acc)[kPV], const TC (&X)[4], const TC (&Y)[4], const TC* __restrict__ w) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < NT; ++u) {
         const TC wu = w[u];
 #pragma unroll
         for (int p = 0; p < kPV; ++p) {
@@ -139,14 +160,25 @@ __device__ __forceinline__ void vstep(TC (&acc)[kPV], const TC (&X)[4], const TC
     }
 }
 
-// 8 horizontal outputs from a staged row (inputs row[0 .. NP+7]).
+// Partial horizontal step of nt (1..3) taps.
 template <typename TC, typename TS>
-__device__ __forceinline__ void hconv(TC (&acc)[kPH], const TS* row, int NP, const TC* __restrict__ w) {
+__device__ __forceinline__ void hstep_part(int nt, TC (&acc)[kPH], const TS (&X)[4], const TS (&Y)[4],
+                                           const TS (&Z)[4], const TC* __restrict__ w) {
+    if (nt == 1) hstep<1>(acc, X, Y, Z, w);
+    else if (nt == 2) hstep<2>(acc, X, Y, Z, w);
+    else hstep<3>(acc, X, Y, Z, w);
+}
+
+// 8 horizontal outputs from a staged row: N taps over inputs row[0 .. N+6].
+// Three 4-value buffers rotate through a 3-step unrolled loop, so no window
+// value is ever moved between registers.
+template <typename TC, typename TS>
+__device__ __forceinline__ void hconv(TC (&acc)[kPH], const TS* row, int N, const TC* __restrict__ w) {
     TS A[4], B[4], C[4];
     load4_row(row, A);
     load4_row(row + 4, B);
     int j0 = 0;
-    for (; j0 + 12 <= NP; j0 += 12) {
+    for (; j0 + 12 <= N; j0 += 12) {
         load4_row(row + j0 + 8, C);
         hstep(acc, A, B, C, w + j0);
         load4_row(row + j0 + 12, A);
@@ -154,33 +186,52 @@ __device__ __forceinline__ void hconv(TC (&acc)[kPH], const TS* row, int NP, con
         load4_row(row + j0 + 16, B);
         hstep(acc, C, A, B, w + j0 + 8);
     }
-    const int rem = NP - j0;  // 0, 4 or 8
-    if (rem >= 4) {
-        load4_row(row + j0 + 8, C);
-        hstep(acc, A, B, C, w + j0);
-        if (rem == 8) {
-            load4_row(row + j0 + 12, A);
-            hstep(acc, B, C, A, w + j0 + 4);
-        }
-    }
+    int left = N - j0;  // 0..11, window state (A, B)
+    if (left == 0) return;
+    load4_row(row + j0 + 8, C);
+    if (left < 4) { hstep_part(left, acc, A, B, C, w + j0); return; }
+    hstep(acc, A, B, C, w + j0);
+    j0 += 4; left -= 4;  // state (B, C)
+    if (left == 0) return;
+    load4_row(row + j0 + 8, A);
+    if (left < 4) { hstep_part(left, acc, B, C, A, w + j0); return; }
+    hstep(acc, B, C, A, w + j0);
+    j0 += 4; left -= 4;  // state (C, A), left 0..3
+    if (left == 0) return;
+    load4_row(row + j0 + 8, B);
+    hstep_part(left, acc, C, A, B, w + j0);
 }
 
-// 4 vertical outputs from an intermediate column (inputs col[0 .. NP+3] rows).
-template <int IP, typename TC>
-__device__ __forceinline__ void vconv(TC (&acc)[kPV], const TC* col, int NP, const TC* __restrict__ w) {
+template <typename TC>
+__device__ __forceinline__ void vstep_part(int nt, TC (&acc)[kPV], const TC (&X)[4], const TC (&Y)[4],
+                                           const TC* __restrict__ w) {
+    if (nt == 1) vstep<1>(acc, X, Y, w);
+    else if (nt == 2) vstep<2>(acc, X, Y, w);
+    else vstep<3>(acc, X, Y, w);
+}
+
+// 4 vertical outputs from a column of the (column-major) intermediate: N
+// taps over col[0 .. N+2]; two buffers alternate through a 2-step loop.
+template <typename TC>
+__device__ __forceinline__ void vconv(TC (&acc)[kPV], const TC* col, int N, const TC* __restrict__ w) {
     TC A[4], B[4];
-    load4_col<IP>(col, A);
+    load4_row(col, A);
     int j0 = 0;
-    for (; j0 + 8 <= NP; j0 += 8) {
-        load4_col<IP>(col + (j0 + 4) * IP, B);
+    for (; j0 + 8 <= N; j0 += 8) {
+        load4_row(col + j0 + 4, B);
         vstep(acc, A, B, w + j0);
-        load4_col<IP>(col + (j0 + 8) * IP, A);
+        load4_row(col + j0 + 8, A);
         vstep(acc, B, A, w + j0 + 4);
     }
-    if (j0 < NP) {
-        load4_col<IP>(col + (j0 + 4) * IP, B);
-        vstep(acc, A, B, w + j0);
-    }
+    int left = N - j0;  // 0..7, state A
+    if (left == 0) return;
+    load4_row(col + j0 + 4, B);
+    if (left < 4) { vstep_part(left, acc, A, B, w + j0); return; }
+    vstep(acc, A, B, w + j0);
+    j0 += 4; left -= 4;  // state B
+    if (left == 0) return;
+    load4_row(col + j0 + 4, A);
+    vstep_part(left, acc, B, A, w + j0);
 }
 
 // Stage padded-tile rows [s0, s0+rows) of one channel into LDS.  Lanes walk
@@ -191,7 +242,7 @@ template <typename TIn, typename TS>
 __device__ __forceinline__ void stage_rows(TS* tile, int TP, const TIn* plane, int64_t ish, int64_t isw, int y_first,
                                            int x_first, int s0, int rows, int TW, int h, int w) {
     constexpr int RB = 8, KB = 2, kWaves = kThreads / 64;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
     for (int k0 = 0; k0 < TW; k0 += 64 * KB) {
         uint32_t coff[KB];
         bool cv[KB];
@@ -227,6 +278,48 @@ __device__ __forceinline__ void stage_rows(TS* tile, int TP, const TIn* plane, i
     }
 }
 
+// 8-bit input staged as exact fp16, two columns per lane and one 32-bit LDS
+// write per pair: the bytes b0, b1 are placed under the fp16 exponent of 1024
+// (bits 0x6400 | b encode 1024 + b exactly) and 1024 is subtracted from both
+// halves at once.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+template <>
+__device__ __forceinline__ void stage_rows<uint8_t, _Float16>(_Float16* tile, int TP, const uint8_t* plane,
+                                                             int64_t ish, int64_t isw, int y_first, int x_first,
+                                                             int s0, int rows, int TW, int h, int w) {
+    constexpr int RB = 8, kWaves = kThreads / 64;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const half2_t bias = {(_Float16)1024.0f, (_Float16)1024.0f};
+    for (int k0 = 0; k0 < TW; k0 += 128) {
+        const int tx = k0 + 2 * lane;  // this lane's first column; tx + 1 < TP always
+        const bool cv = tx < TW;
+        const uint32_t c0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * (uint32_t)isw;
+        const uint32_t c1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * (uint32_t)isw;
+        for (int t0 = wave; t0 < rows; t0 += kWaves * RB) {
+            uint32_t b0[RB], b1[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int ty = t0 + rb * kWaves;
+                if (ty < rows && cv) {
+                    const uint8_t* rp = plane + (int64_t)clampi(y_first + s0 + ty, 0, h - 1) * ish;
+                    b0[rb] = rp[c0];
+                    b1[rb] = rp[c1];
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int ty = t0 + rb * kWaves;
+                if (ty < rows && cv) {
+                    const uint32_t bits = (b1[rb] << 16) | b0[rb] | 0x64006400u;
+                    const half2_t hv = __builtin_bit_cast(half2_t, bits) - bias;
+                    *reinterpret_cast<half2_t*>(tile + ty * TP + tx) = hv;
+                }
+            }
+        }
+    }
+}
+
 struct FragLoc {
     int f, lb, bx, by, xa, ya, bw, bh;
 };
@@ -249,18 +342,17 @@ __device__ __forceinline__ FragLoc locate(const FwdLaunch& a, int gid) {
     return L;
 }
 
-template <typename TIn, typename TOut, typename TS, typename TC, int BMAX>
+template <typename TIn, typename TOut, typename TS, typename TC>
 __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, const int32_t* __restrict__ radius,
                                                            const TC* __restrict__ wts,
                                                            const int32_t* __restrict__ order) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int IP = BMAX + 4;
     const int gid = order[blockIdx.x];
     const FragLoc L = locate(a, gid);
     const TIn* in = static_cast<const TIn*>(a.in.data) + (int64_t)(a.frame_base + L.f) * a.in.sn;
     TOut* out = static_cast<TOut*>(a.out.data) + (int64_t)(a.frame_base + L.f) * a.out.sn;
     const int r = radius[gid];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63;
     constexpr int kWaves = kThreads / 64;
 
     if (r == 0) {  // foveal fragment: copied (Appendix "Workload of the Block")
@@ -279,7 +371,8 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
     const int SR = min(a.strip_rows, g.TH);
     const int TP = tile_pitch(g.TW, sizeof(TS));
     TS* tile = reinterpret_cast<TS*>(smem);
-    TC* inter = reinterpret_cast<TC*>(smem + align16((size_t)SR * TP * sizeof(TS)));
+    const int IP = inter_pitch(g.TH, sizeof(TC));
+    TC* inter = reinterpret_cast<TC*>(smem + align16((size_t)SR * TP * sizeof(TS)));  // [column][row]
 
     for (int c = 0; c < a.c; ++c) {
         const TIn* plane = in + c * a.in.sc;
@@ -298,10 +391,10 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
                 TC acc[kPH];
 #pragma unroll
                 for (int p = 0; p < kPH; ++p) acc[p] = 0;
-                hconv(acc, tile + ty * TP + x0, g.NP, w);
-                TC* dst = inter + (s0 + ty) * IP + x0;
+                hconv(acc, tile + ty * TP + x0, g.N, w);
+                TC* dst = inter + x0 * IP + s0 + ty;
 #pragma unroll
-                for (int p = 0; p < kPH; ++p) dst[p] = acc[p];
+                for (int p = 0; p < kPH; ++p) dst[p * IP] = acc[p];
             }
         }
         __syncthreads();
@@ -311,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
             TC acc[kPV];
 #pragma unroll
             for (int p = 0; p < kPV; ++p) acc[p] = 0;
-            vconv<IP>(acc, inter + y0 * IP + x, g.NP, w);
+            vconv(acc, inter + x * IP + y0, g.N, w);
             TOut* o = oc + (int64_t)(L.xa + x) * a.out.sw;
 #pragma unroll
             for (int p = 0; p < kPV; ++p)
@@ -335,14 +428,28 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
     if (lane == 0) radius[gid] = r;
     const int N = 2 * r + 1;
     const double inv = r > 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
+    constexpr int kHeld = 4;  // taps per lane kept in registers
+    double g[kHeld];
     double part = 0.0;
-    for (int j = lane; j < N; j += 64) {
+#pragma unroll
+    for (int q = 0; q < kHeld; ++q) {
+        const int j = lane + 64 * q;
+        const double k = (double)(j - r);
+        g[q] = j < N ? exp(-(k * k) * inv) : 0.0;
+        part += g[q];
+    }
+    for (int j = lane + 64 * kHeld; j < N; j += 64) {
         const double k = (double)(j - r);
         part += exp(-(k * k) * inv);
     }
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
     TC* wr = wts + (size_t)gid * a.wstride;
-    for (int j = lane; j < a.wstride; j += 64) {
+#pragma unroll
+    for (int q = 0; q < kHeld; ++q) {
+        const int j = lane + 64 * q;
+        if (j < a.wstride) wr[j] = (TC)(g[q] / part);
+    }
+    for (int j = lane + 64 * kHeld; j < a.wstride; j += 64) {
         double v = 0.0;
         if (j < N) {
             const double k = (double)(j - r);
@@ -360,23 +467,31 @@ constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 1024;
 
 __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t* __restrict__ radius, int n,
-                                                                  int32_t* __restrict__ order) {
+                                                                  int nbins, int32_t* __restrict__ order) {
     __shared__ int bins[kOrderBins];
-    for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) bins[i] = 0;
+    for (int i = threadIdx.x; i < nbins; i += kOrderThreads) bins[i] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kOrderThreads) atomicAdd(&bins[min(radius[i], kOrderBins - 1)], 1);
+    for (int i = threadIdx.x; i < n; i += kOrderThreads) atomicAdd(&bins[min(radius[i], nbins - 1)], 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int b = kOrderBins - 1; b >= 0; --b) {
-            const int cnt = bins[b];
-            bins[b] = run;
-            run += cnt;
+    if (threadIdx.x < 64) {
+        // exclusive scan from the largest radius down, 64 bins per step
+        const int lane = threadIdx.x;
+        int carry = 0;
+        for (int b0 = 0; b0 < nbins; b0 += 64) {
+            const int b = nbins - 1 - (b0 + lane);
+            const int v = b >= 0 ? bins[b] : 0;
+            int incl = v;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += t;
+            }
+            if (b >= 0) bins[b] = carry + incl - v;
+            carry += __shfl(incl, 63, 64);
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += kOrderThreads) {
-        const int pos = atomicAdd(&bins[min(radius[i], kOrderBins - 1)], 1);
+        const int pos = atomicAdd(&bins[min(radius[i], nbins - 1)], 1);
         order[pos] = i;
     }
 }
@@ -391,40 +506,35 @@ __global__ void fov_plan_kernel(FrameParams fp, int n, double* sigma_out, int32_
     r_out[b] = radius_of(s);
 }
 
-template <typename TIn, typename TOut, typename TS, typename TC, int BMAX>
+template <typename TIn, typename TOut, typename TS, typename TC>
 struct FwdSlot {
     static bool configured;
 };
-template <typename TIn, typename TOut, typename TS, typename TC, int BMAX>
-bool FwdSlot<TIn, TOut, TS, TC, BMAX>::configured = false;
+template <typename TIn, typename TOut, typename TS, typename TC>
+bool FwdSlot<TIn, TOut, TS, TC>::configured = false;
 
 template <typename TIn, typename TOut, typename TS, typename TC>
 fov_status launch_typed(const FwdLaunch& a, int nblocks, size_t lds, const PlanBuffers& plan, hipStream_t stream,
-                        size_t lds_limit, int bmax) {
+                        size_t lds_limit) {
     TC* wts = static_cast<TC*>(plan.weights);
     hipLaunchKernelGGL(fov_plan_weights_kernel<TC>, dim3(nblocks), dim3(64), 0, stream, a, plan.radius, wts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "plan kernel launch");
     hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.radius,
-                       nblocks, plan.order);
+                       nblocks, std::min(a.r_cap + 1, kOrderBins), plan.order);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "order kernel launch");
-    auto run = [&](auto kern, bool& configured) -> fov_status {
-        if (!configured) {
-            hipError_t e2 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                (int)lds_limit);
-            if (e2 != hipSuccess) return hip_error(e2, "hipFuncSetAttribute(forward)");
-            configured = true;
-        }
-        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreads), lds, stream, a, (const int32_t*)plan.radius,
-                           (const TC*)wts, (const int32_t*)plan.order);
-        hipError_t e3 = hipGetLastError();
-        if (e3 != hipSuccess) return hip_error(e3, "forward kernel launch");
-        return FOV_OK;
-    };
-    if (bmax <= 32)
-        return run(fov_fwd_kernel<TIn, TOut, TS, TC, 32>, FwdSlot<TIn, TOut, TS, TC, 32>::configured);
-    return run(fov_fwd_kernel<TIn, TOut, TS, TC, 64>, FwdSlot<TIn, TOut, TS, TC, 64>::configured);
+    auto kern = fov_fwd_kernel<TIn, TOut, TS, TC>;
+    if (!FwdSlot<TIn, TOut, TS, TC>::configured) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
+        if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(forward)");
+        FwdSlot<TIn, TOut, TS, TC>::configured = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreads), lds, stream, a, (const int32_t*)plan.radius,
+                       (const TC*)wts, (const int32_t*)plan.order);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "forward kernel launch");
+    return FOV_OK;
 }
 
 int stage_size(int in_dtype) { return in_dtype == FOV_U8 ? 2 : (in_dtype == FOV_F32 ? 4 : 8); }
@@ -446,26 +556,23 @@ PlanBuffers carve_plan(void* ws, int nfrag) {
 }
 
 size_t forward_lds_bytes(int in_dtype, int r_cap, int B, int strip_rows) {
-    const int bmax = B <= 32 ? 32 : 64;
     const Geom g = geom(r_cap, B, B);
     const int rows = strip_rows < g.TH ? strip_rows : g.TH;
     const int es = stage_size(in_dtype), ec = compute_size(in_dtype);
-    return align16((size_t)rows * tile_pitch(g.TW, es) * es) + (size_t)g.TH * inter_pitch(bmax) * ec + 64;
+    return align16((size_t)rows * tile_pitch(g.TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec + 64;
 }
 
 fov_status launch_forward(const FwdLaunch& a, int nblocks, int in_dtype, int out_dtype, size_t lds,
                           const PlanBuffers& plan, hipStream_t stream, size_t lds_limit) {
     if (nblocks <= 0) return FOV_OK;
-    int bmax = 1;
-    for (int i = 0; i < a.nframes; ++i) bmax = std::max(bmax, a.fr[i].block);
     if (in_dtype == FOV_U8 && out_dtype == FOV_U8)
-        return launch_typed<uint8_t, uint8_t, _Float16, float>(a, nblocks, lds, plan, stream, lds_limit, bmax);
+        return launch_typed<uint8_t, uint8_t, _Float16, float>(a, nblocks, lds, plan, stream, lds_limit);
     if (in_dtype == FOV_U8 && out_dtype == FOV_F32)
-        return launch_typed<uint8_t, float, _Float16, float>(a, nblocks, lds, plan, stream, lds_limit, bmax);
+        return launch_typed<uint8_t, float, _Float16, float>(a, nblocks, lds, plan, stream, lds_limit);
     if (in_dtype == FOV_F32 && out_dtype == FOV_F32)
-        return launch_typed<float, float, float, float>(a, nblocks, lds, plan, stream, lds_limit, bmax);
+        return launch_typed<float, float, float, float>(a, nblocks, lds, plan, stream, lds_limit);
     if (in_dtype == FOV_F64 && out_dtype == FOV_F64)
-        return launch_typed<double, double, double, double>(a, nblocks, lds, plan, stream, lds_limit, bmax);
+        return launch_typed<double, double, double, double>(a, nblocks, lds, plan, stream, lds_limit);
     return set_error(FOV_EDTYPE, "unsupported dtype pair");
 }
 
