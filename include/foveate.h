@@ -121,9 +121,28 @@ fov_status foveate_plan_host(int32_t h, int32_t w, const fov_params* p, double* 
  *   stream  : hipStream_t (NULL = default stream).
  * Empty views (any extent 0) are a no-op.  Fails with FOV_ERANGE when a
  * fragment's radius needs more on-chip memory than one workgroup may use.
+ * The library keeps a per-(device, stream) workspace for fragment plans (grown
+ * with hipMalloc on first use or when a call needs more); calls on one stream
+ * are ordered and may share it, calls on different streams use their own.
  */
 fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fov_params* p,
                            int32_t np, void* stream);
+
+/*
+ * Foveate nframes frames of possibly different sizes in one launch: the
+ * fragments of all frames form one queue, ordered by decreasing radius (their
+ * cost), that a persistent grid drains (Alg. 1 run over a batch; each frame
+ * keeps its own fixation and ramp).
+ *   ins[i], outs[i] : views of one frame each (n == 1), any (c, h, w) and
+ *                     strides; all frames share one dtype pair (as forward).
+ *                     No output may overlap any input or another output.
+ *   ps[i]           : parameters of frame i.
+ * Frame descriptors beyond 16 are uploaded from a library-owned pinned buffer
+ * to the library's per-stream workspace.  Asynchronous on `stream`; caller
+ * buffers must stay alive until the stream reaches this work.
+ */
+fov_status foveate_forward_batch(const fov_tensor* ins, const fov_tensor* outs, const fov_params* ps,
+                                 int32_t nframes, void* stream);
 
 /*
  * Adjoint (transpose) of foveate_forward for the same parameters:

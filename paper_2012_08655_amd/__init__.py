@@ -17,7 +17,7 @@ def load():
 def __getattr__(name):
     # The torch binding is imported lazily so that loading the C library (and
     # checking its exports) does not require torch.
-    if name in ("forward", "backward", "grid", "plan_device", "plan_host", "foveate", "FoveateFn",
+    if name in ("forward", "forward_batch", "backward", "grid", "plan_device", "plan_host", "foveate", "FoveateFn",
                 "tensor_desc"):
         from . import api
         return getattr(api, name)

@@ -94,6 +94,30 @@ def forward(x: torch.Tensor, params, out: torch.Tensor | None = None, layout: st
     return out
 
 
+def forward_batch(frames, params, outs=None, layout: str = "HWC", out_dtype: torch.dtype | None = None,
+                  stream=None):
+    """Foveate a list of frames of possibly different sizes in one launch.
+
+    ``frames`` and ``outs`` are lists of single-frame tensors in ``layout``
+    ("HWC", "CHW" or "HW"); ``params`` is one dict per frame.  Returns outs.
+    """
+    n = len(frames)
+    if len(params) != n:
+        raise ValueError("need one params dict per frame")
+    if outs is None:
+        outs = [torch.empty_like(f, dtype=out_dtype or f.dtype) for f in frames]
+    di = (N.FovTensor * max(n, 1))(*[tensor_desc(f, layout) for f in frames])
+    do = (N.FovTensor * max(n, 1))(*[tensor_desc(o, layout) for o in outs])
+    arr = (N.FovParams * max(n, 1))()
+    keep = []
+    for i, p in enumerate(params):
+        a, _, k = _params_array(p, 1)
+        arr[i] = a[0]
+        keep.append(k)
+    N.check(N.lib().foveate_forward_batch(di, do, arr, n, _stream_handle(stream)))
+    return outs
+
+
 def backward(grad_out: torch.Tensor, params, grad_in: torch.Tensor | None = None, layout: str = "NCHW",
              stream=None) -> torch.Tensor:
     """grad_in = A^T grad_out for the same parameters as the forward."""

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "adjoint.h"
 #include "common.h"
@@ -74,40 +75,71 @@ fov_status device_info(const DeviceInfo** out) {
 
 namespace {
 
-// Library-owned device workspace, one per (device, stream): work queued on one
-// stream is ordered, so consecutive calls on that stream may reuse it.  It
-// only grows; before freeing a smaller one the stream is drained.
+// Library-owned workspace, one per (device, stream): work queued on one stream
+// is ordered, so consecutive calls on that stream may reuse it.  It holds a
+// device buffer (plans, queues, frame tables) and a pinned host buffer for
+// uploading frame tables.  Both only grow; before a device buffer in use is
+// freed the stream is drained, and before the pinned buffer is rewritten the
+// previous upload from it is waited for.
 struct Workspace {
-    void* ptr = nullptr;
-    size_t bytes = 0;
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    void* host = nullptr;
+    size_t host_bytes = 0;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
-fov_status workspace(hipStream_t stream, size_t bytes, void** out) {
+fov_status workspace(hipStream_t stream, size_t dev_bytes, size_t host_bytes, Workspace** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_error(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace& w = g_ws[{dev, stream}];
-    if (w.bytes < bytes) {
-        if (w.ptr) {
+    if (w.dev_bytes < dev_bytes) {
+        if (w.dev) {
             e = hipStreamSynchronize(stream);
             if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize(workspace growth)");
-            e = hipFree(w.ptr);
+            e = hipFree(w.dev);
             if (e != hipSuccess) return hip_error(e, "hipFree(workspace)");
-            w.ptr = nullptr;
-            w.bytes = 0;
+            w.dev = nullptr;
+            w.dev_bytes = 0;
         }
-        size_t nb = std::max(bytes, (size_t)1 << 20);
-        e = hipMalloc(&w.ptr, nb);
+        const size_t nb = std::max(dev_bytes, (size_t)1 << 20);
+        e = hipMalloc(&w.dev, nb);
         if (e != hipSuccess) {
-            w.ptr = nullptr;
+            w.dev = nullptr;
             return set_error(FOV_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
         }
-        w.bytes = nb;
+        w.dev_bytes = nb;
     }
-    *out = w.ptr;
+    if (host_bytes > 0 && w.host_bytes < host_bytes) {
+        if (w.host) {
+            if (w.upload_pending) {
+                e = hipEventSynchronize(w.upload_done);
+                if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(upload)");
+                w.upload_pending = false;
+            }
+            e = hipHostFree(w.host);
+            if (e != hipSuccess) return hip_error(e, "hipHostFree(staging)");
+            w.host = nullptr;
+            w.host_bytes = 0;
+        }
+        const size_t nb = std::max(host_bytes, (size_t)1 << 16);
+        e = hipHostMalloc(&w.host, nb, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            w.host = nullptr;
+            return set_error(FOV_ENOMEM, std::string("pinned staging allocation failed: ") + hipGetErrorString(e));
+        }
+        w.host_bytes = nb;
+        if (!w.upload_done) {
+            e = hipEventCreateWithFlags(&w.upload_done, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_error(e, "hipEventCreate");
+        }
+    }
+    *out = &w;
     return FOV_OK;
 }
 
@@ -205,23 +237,20 @@ int frame_r_max(const FrameParams& f, int h) {
     return r;
 }
 
-// Padded-tile rows resident in LDS at once.  FOV_STRIP_ROWS forces a value;
-// otherwise the whole tile when it fits the per-workgroup LDS target (so that
-// several workgroups share a CU), else the tallest multiple of 8 rows that
-// does, else the tallest that fits the device limit at all.
-int choose_strip_rows(int in_dtype, int r_cap, int B, size_t lds_limit) {
+// Dispatch of the main forward kernel: FOV_PERSISTENT=1 selects the
+// persistent grid; by default each fragment is its own workgroup (measured
+// faster on MI355X for single frames and batches alike).
+bool dispatch_persistent() {
+    static const bool v = env_int("FOV_PERSISTENT", 0) != 0;
+    return v;
+}
+
+// Padded-tile rows resident in LDS at once: the kernel's strip height (64
+// rows, four rows per lane of a wave) unless FOV_STRIP_ROWS asks for fewer.
+int choose_strip_rows() {
     static const int forced = env_int("FOV_STRIP_ROWS", 0);
-    if (forced > 0) return forced;
-    static const size_t target = (size_t)std::max(16, env_int("FOV_LDS_TARGET_KB", 64)) * 1024;
-    const int full = 1 << 20;
-    if (forward_lds_bytes(in_dtype, r_cap, B, full) <= target) return full;
-    for (size_t lim : {target, lds_limit}) {
-        int best = 0;
-        for (int sr = 8; sr <= 512; sr += 8)
-            if (forward_lds_bytes(in_dtype, r_cap, B, sr) <= lim) best = sr;
-        if (best > 0) return best;
-    }
-    return 8;
+    const int mx = forward_strip_max();
+    return forced > 0 && forced < mx ? forced : mx;
 }
 
 }  // namespace
@@ -295,50 +324,125 @@ static fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov
     return FOV_OK;
 }
 
+// One persistent forward launch over a list of frames (any shapes, one dtype
+// pair).  Up to kArgFrames descriptors travel in the kernel arguments; more
+// are uploaded as a device table from pinned memory.
+static fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream) {
+    fov_status s;
+    const DeviceInfo* dev = nullptr;
+    if ((s = device_info(&dev)) != FOV_OK) return s;
+    const int nf = (int)frames.size();
+    if (nf == 0) return FOV_OK;
+    std::vector<int32_t> prefix(nf + 1);
+    int64_t total = 0;
+    int r_cap = 0, bmax = 1;
+    for (int i = 0; i < nf; ++i) {
+        prefix[i] = (int32_t)total;
+        total += (int64_t)frames[i].p.nbx * frames[i].nby;
+        r_cap = std::max(r_cap, frame_r_max(frames[i].p, frames[i].h));
+        bmax = std::max(bmax, frames[i].p.block);
+    }
+    if (total > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
+    prefix[nf] = (int32_t)total;
+    const int sr = choose_strip_rows();
+    const size_t lds = forward_lds_bytes(in_dtype, r_cap, bmax, sr);
+    if (lds + 64 > dev->lds_limit)
+        return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
+                                         " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
+    const int wsize = in_dtype == FOV_F64 ? 8 : 4;
+    FwdLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.nframes = nf;
+    a.nfrag = (int32_t)total;
+    a.r_cap = r_cap;
+    a.strip_rows = sr;
+    a.wstride = round_up(2 * r_cap + 1, 16);
+    const size_t pbytes = (plan_bytes(a.nfrag, a.wstride, wsize) + 255) / 256 * 256;
+    const bool upload = nf > kArgFrames;
+    const size_t tbytes = ((size_t)nf * sizeof(FrameDesc) + (size_t)(nf + 1) * 4 + 255) / 256 * 256;
+    Workspace* ws = nullptr;
+    if ((s = workspace(stream, pbytes + tbytes, upload ? tbytes : 0, &ws)) != FOV_OK) return s;
+    const PlanBuffers plan = carve_plan(ws->dev, a.nfrag, a.wstride, wsize);
+    char* dtab = static_cast<char*>(ws->dev) + pbytes;
+    a.table = reinterpret_cast<FrameDesc*>(dtab);
+    a.prefix = reinterpret_cast<int32_t*>(dtab + (size_t)nf * sizeof(FrameDesc));
+    if (upload) {
+        if (ws->upload_pending) {
+            hipError_t e = hipEventSynchronize(ws->upload_done);
+            if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(upload)");
+            ws->upload_pending = false;
+        }
+        char* hst = static_cast<char*>(ws->host);
+        std::memcpy(hst, frames.data(), (size_t)nf * sizeof(FrameDesc));
+        std::memcpy(hst + (size_t)nf * sizeof(FrameDesc), prefix.data(), (size_t)(nf + 1) * 4);
+        hipError_t e = hipMemcpyAsync(dtab, hst, tbytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(frame table)");
+        e = hipEventRecord(ws->upload_done, stream);
+        if (e != hipSuccess) return hip_error(e, "hipEventRecord(upload)");
+        ws->upload_pending = true;
+    } else {
+        a.from_args = 1;
+        for (int i = 0; i < nf; ++i) a.fr[i] = frames[i];
+        for (int i = 0; i <= nf; ++i) a.kprefix[i] = prefix[i];
+    }
+    return launch_forward(a, in_dtype, out_dtype, lds, plan, stream, dev->lds_limit, dev->cus, dispatch_persistent());
+}
+
+static FrameDesc frame_desc(const fov_tensor& in, const fov_tensor& out, int n, const fov_params& p) {
+    const size_t ei = dtype_size(in.dtype), eo = dtype_size(out.dtype);
+    FrameDesc d;
+    d.in = static_cast<const char*>(in.data) + (size_t)n * in.sn * ei;
+    d.out = static_cast<char*>(out.data) + (size_t)n * out.sn * eo;
+    d.isc = in.sc; d.ish = in.sh; d.isw = in.sw;
+    d.osc = out.sc; d.osh = out.sh; d.osw = out.sw;
+    d.c = in.c; d.h = in.h; d.w = in.w;
+    d.p = to_frame(p, in.h, in.w);
+    d.nby = grid_extent(in.h, p.origin_y, p.block);
+    return d;
+}
+
 fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
                            void* stream) {
     bool empty = false;
     fov_status s = prepare(in, out, p, np, false, &empty);
     if (s != FOV_OK || empty) return s;
-    const DeviceInfo* dev = nullptr;
-    if ((s = device_info(&dev)) != FOV_OK) return s;
-    const int wsize = in->dtype == FOV_F64 ? 8 : 4;
+    std::vector<FrameDesc> frames;
+    frames.reserve(in->n);
+    for (int i = 0; i < in->n; ++i) frames.push_back(frame_desc(*in, *out, i, p[np == 1 ? 0 : i]));
+    return run_forward(frames, in->dtype, out->dtype, (hipStream_t)stream);
+}
 
-    for (int f0 = 0; f0 < in->n; f0 += kMaxFramesPerLaunch) {
-        const int nf = std::min(kMaxFramesPerLaunch, in->n - f0);
-        FwdLaunch a;
-        std::memset(&a, 0, sizeof(a));
-        a.in = View{in->data, in->sn, in->sc, in->sh, in->sw};
-        a.out = View{out->data, out->sn, out->sc, out->sh, out->sw};
-        a.c = in->c; a.h = in->h; a.w = in->w;
-        a.nframes = nf;
-        a.frame_base = f0;
-        int r_cap = 0, bmax = 1, total = 0;
-        for (int i = 0; i < nf; ++i) {
-            const fov_params& pp = p[np == 1 ? 0 : f0 + i];
-            a.fr[i] = to_frame(pp, in->h, in->w);
-            a.blk_prefix[i] = total;
-            total += a.fr[i].nbx * grid_extent(in->h, pp.origin_y, pp.block);
-            r_cap = std::max(r_cap, frame_r_max(a.fr[i], in->h));
-            bmax = std::max(bmax, pp.block);
-        }
-        a.blk_prefix[nf] = total;
-        a.r_cap = r_cap;
-        a.wstride = round_up(2 * r_cap + 1, 16);
-        const int sr = choose_strip_rows(in->dtype, r_cap, bmax, dev->lds_limit);
-        a.strip_rows = sr;
-        const size_t lds = forward_lds_bytes(in->dtype, r_cap, bmax, sr);
-        if (lds > dev->lds_limit)
-            return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
-                                             " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
-        void* ws = nullptr;
-        if ((s = workspace((hipStream_t)stream, plan_bytes(total, a.wstride, wsize), &ws)) != FOV_OK) return s;
-        const PlanBuffers plan = carve_plan(ws, total);
-        if ((s = launch_forward(a, total, in->dtype, out->dtype, lds, plan, (hipStream_t)stream, dev->lds_limit)) !=
-            FOV_OK)
-            return s;
+fov_status foveate_forward_batch(const fov_tensor* ins, const fov_tensor* outs, const fov_params* ps,
+                                 int32_t nframes, void* stream) {
+    if (nframes < 0) return set_error(FOV_EINVAL, "nframes < 0");
+    if (nframes == 0) return FOV_OK;
+    if (!ins || !outs || !ps) return set_error(FOV_EINVAL, "NULL argument");
+    std::vector<FrameDesc> frames;
+    frames.reserve(nframes);
+    int dt_in = -1, dt_out = -1;
+    for (int i = 0; i < nframes; ++i) {
+        bool empty = false;
+        fov_status s = prepare(&ins[i], &outs[i], &ps[i], 1, false, &empty);
+        if (s != FOV_OK) return set_error(s, "frame " + std::to_string(i) + ": " + g_last_error);
+        if (empty) continue;
+        if (ins[i].n != 1) return set_error(FOV_EINVAL, "frame " + std::to_string(i) + ": each view must hold one frame");
+        if (dt_in < 0) { dt_in = ins[i].dtype; dt_out = outs[i].dtype; }
+        if (ins[i].dtype != dt_in || outs[i].dtype != dt_out)
+            return set_error(FOV_EDTYPE, "all frames of a batch must share one dtype pair");
+        frames.push_back(frame_desc(ins[i], outs[i], 0, ps[i]));
     }
-    return FOV_OK;
+    // outputs of different frames must not overlap inputs of others either
+    for (int i = 0; i < nframes; ++i)
+        for (int j = 0; j < nframes; ++j) {
+            if (i == j || is_empty(ins[j]) || is_empty(outs[i])) continue;
+            fov_status s = check_alias(ins[j], outs[i]);
+            if (s != FOV_OK) return set_error(s, "output of frame " + std::to_string(i) + " overlaps input of frame " + std::to_string(j));
+            if (j < i) {
+                s = check_alias(outs[j], outs[i]);
+                if (s != FOV_OK) return set_error(s, "outputs of frames " + std::to_string(j) + " and " + std::to_string(i) + " overlap");
+            }
+        }
+    return run_forward(frames, dt_in, dt_out, (hipStream_t)stream);
 }
 
 fov_status foveate_backward(const fov_tensor* grad_out, const fov_tensor* grad_in, const fov_params* p, int32_t np,

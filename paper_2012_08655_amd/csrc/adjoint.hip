@@ -19,7 +19,6 @@
 #include <algorithm>
 #include <cstring>
 
-#include "forward.h"
 
 namespace fov {
 
@@ -57,7 +56,7 @@ __device__ __forceinline__ double folded(int p, int q, int r, int L, const doubl
 constexpr int kMaxOut = (kMaxBlock * kMaxBlock + kThreads - 1) / kThreads;
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fov_adj_kernel(const FwdLaunch a) {
+__global__ __launch_bounds__(kThreads) void fov_adj_kernel(const AdjLaunch a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int gid = blockIdx.x;
     int f = 0;
@@ -174,7 +173,7 @@ template <typename T>
 bool AdjSlot<T>::configured = false;
 
 template <typename T>
-fov_status launch_adj_typed(const FwdLaunch& a, int nblocks, size_t lds, hipStream_t stream, size_t lds_limit) {
+fov_status launch_adj_typed(const AdjLaunch& a, int nblocks, size_t lds, hipStream_t stream, size_t lds_limit) {
     auto kern = fov_adj_kernel<T>;
     if (!AdjSlot<T>::configured) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
@@ -198,7 +197,7 @@ fov_status launch_adjoint_all(const fov_tensor* go, const fov_tensor* gi, const 
     const int es = go->dtype == FOV_F64 ? 8 : 4;
     for (int f0 = 0; f0 < go->n; f0 += kMaxFramesPerLaunch) {
         const int nf = std::min(kMaxFramesPerLaunch, go->n - f0);
-        FwdLaunch a;
+        AdjLaunch a;
         std::memset(&a, 0, sizeof(a));
         a.in = View{go->data, go->sn, go->sc, go->sh, go->sw};
         a.out = View{gi->data, gi->sn, gi->sc, gi->sh, gi->sw};

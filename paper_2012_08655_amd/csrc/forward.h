@@ -1,43 +1,63 @@
-// Launch interface of the forward and plan kernels.
+// Launch interface of the forward kernels.
 #pragma once
 
 #include "common.h"
 
 namespace fov {
 
-// Kernel arguments of one forward launch: up to kMaxFramesPerLaunch frames of
-// one (c, h, w) shape, each with its own parameters.  Fragments of all frames
-// are numbered consecutively; blk_prefix[f] is the first fragment of frame f.
+// One frame of a forward launch: where it lives, its shape and parameters.
+struct FrameDesc {
+    const void* in;  // first element of this frame's input
+    void* out;       // first element of this frame's output
+    int64_t isc, ish, isw, osc, osh, osw;  // element strides
+    int32_t c, h, w, nby;
+    FrameParams p;  // p.nbx filled in
+};
+
+// Frames whose descriptors travel inside the kernel arguments; larger
+// batches pass a device table instead.
+constexpr int kArgFrames = 16;
+
+// Kernel arguments shared by the plan, order and main forward kernels.
+// Fragments of all frames are numbered consecutively: frame f owns fragments
+// [prefix[f], prefix[f+1]).
 struct FwdLaunch {
-    View in, out;
-    int32_t c, h, w;
-    int32_t nframes;     // frames in this launch
-    int32_t frame_base;  // index (along n) of the first frame of this launch
+    int32_t nframes, nfrag;
     int32_t r_cap;       // largest radius the LDS allocation was sized for
     int32_t strip_rows;  // padded-tile rows staged in LDS at once
     int32_t wstride;     // weights per fragment in the plan workspace (multiple of 16)
-    int32_t blk_prefix[kMaxFramesPerLaunch + 1];
-    FrameParams fr[kMaxFramesPerLaunch];
+    int32_t from_args;   // 1: fr[]/kprefix[] hold the frames and the plan kernel
+                         // copies them to table/prefix; 0: table/prefix were uploaded
+    FrameDesc* table;    // device table of nframes entries (read by the main kernel)
+    int32_t* prefix;     // device array of nframes+1 entries
+    int32_t kprefix[kArgFrames + 1];
+    FrameDesc fr[kArgFrames];
 };
 static_assert(sizeof(FwdLaunch) <= 4000, "kernel arguments must fit the kernarg segment");
 
-// Plan workspace of one launch: radius per fragment and its normalised taps
-// w[0..N) (N = 2r+1, tap k-r at index k), zero-padded to wstride.
+// Plan workspace of one launch.
 struct PlanBuffers {
-    int32_t* radius;  // [nfrag]
-    int32_t* order;   // [nfrag] fragment ids by decreasing radius (dispatch order)
-    void* weights;    // [nfrag][wstride] of float (u8/f32 launches) or double (f64)
+    int32_t* radius;   // [nfrag] radius of each fragment
+    int32_t* order;    // [nfrag] fragment ids by decreasing radius (queue order)
+    void* weights;     // [nfrag][wstride] normalised taps, float (u8/f32) or double (f64)
 };
 
-// Bytes of plan workspace for nfrag fragments, and its layout.
 size_t plan_bytes(int nfrag, int wstride, int wsize);
-PlanBuffers carve_plan(void* ws, int nfrag);
+PlanBuffers carve_plan(void* ws, int nfrag, int wstride, int wsize);
 
-fov_status launch_forward(const FwdLaunch& a, int nblocks, int in_dtype, int out_dtype, size_t lds,
-                          const PlanBuffers& plan, hipStream_t stream, size_t lds_limit);
+// Plan + order + main kernel for one launch.  persist selects the dispatch of
+// the main kernel: a persistent grid striding over the queue, or one
+// workgroup per fragment handed out by the hardware dispatcher.
+fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,
+                          hipStream_t stream, size_t lds_limit, int cus, bool persist);
+
+// Device plan for foveate_plan(): sigma and radius of every fragment.
 fov_status launch_plan(const FrameParams& fp, int nblk, double* sigma_out, int32_t* r_out, hipStream_t stream);
 
 // LDS bytes a forward workgroup needs for radius r_cap and fragment side B.
 size_t forward_lds_bytes(int in_dtype, int r_cap, int B, int strip_rows);
+
+// Largest strip height the kernel stages at once.
+int forward_strip_max();
 
 }  // namespace fov

@@ -234,209 +234,327 @@ __device__ __forceinline__ void vconv(TC (&acc)[kPV], const TC* col, int N, cons
     vstep_part(left, acc, B, A, w + j0);
 }
 
-// Stage padded-tile rows [s0, s0+rows) of one channel into LDS.  Lanes walk
-// columns (coalesced along x), waves walk rows; each lane's clamped column
-// offset is computed once and added to a wave-uniform row pointer, and loads
-// for 8 rows x 2 column chunks are issued before any is consumed.
+// ---- staging of the padded tile ---------------------------------------------------------------
+// The tile is staged into LDS in strips of at most kStripMax rows.  Each strip
+// is loaded in two halves: issue() starts the global loads into registers
+// (lanes walk columns, so loads coalesce along x; wave w owns rows w, w+4,
+// ...), commit() converts the values and writes them to LDS.  The kernel
+// issues strip k+1 before computing strip k, so load latency hides behind
+// arithmetic.  Columns beyond the prefetched chunks are loaded and written
+// inside commit().
+constexpr int kStripMax = 64;
+constexpr int kRowsPerWave = kStripMax / (kThreads / 64);
+
 template <typename TIn, typename TS>
-__device__ __forceinline__ void stage_rows(TS* tile, int TP, const TIn* plane, int64_t ish, int64_t isw, int y_first,
-                                           int x_first, int s0, int rows, int TW, int h, int w) {
-    constexpr int RB = 8, KB = 2, kWaves = kThreads / 64;
-    const int wave = wave_id(), lane = threadIdx.x & 63;
-    for (int k0 = 0; k0 < TW; k0 += 64 * KB) {
-        uint32_t coff[KB];
-        bool cv[KB];
+struct Stager {
+    static constexpr int KB = 2;  // prefetched 64-column chunks
+    TIn v[kRowsPerWave][KB];
+    uint32_t coff[KB];
+    bool cv[KB];
+    const TIn* plane;
+    int64_t ish, isw;
+    int y0, rows, h, w, x_first, TW;
+
+    __device__ __forceinline__ void setup(int x_first_, int TW_, int w_, int64_t isw_, int64_t ish_, int h_) {
+        x_first = x_first_; TW = TW_; w = w_; isw = isw_; ish = ish_; h = h_;
+        const int lane = threadIdx.x & 63;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
-            const int tx = k0 + kb * 64 + lane;
+            const int tx = kb * 64 + lane;
             cv[kb] = tx < TW;
             coff[kb] = (uint32_t)clampi(x_first + tx, 0, w - 1) * (uint32_t)isw;
         }
-        for (int t0 = wave; t0 < rows; t0 += kWaves * RB) {
-            TIn v[RB][KB];
+    }
+    __device__ __forceinline__ void issue(const TIn* plane_, int y0_, int rows_) {
+        plane = plane_; y0 = y0_; rows = rows_;
+        const int wave = wave_id();
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const int ty = t0 + rb * kWaves;
-                if (ty < rows) {
-                    const TIn* rp = plane + (int64_t)clampi(y_first + s0 + ty, 0, h - 1) * ish;
+        for (int rb = 0; rb < kRowsPerWave; ++rb) {
+            const int ty = wave + rb * (kThreads / 64);
+            if (ty < rows) {
+                const TIn* rp = plane + (int64_t)clampi(y0 + ty, 0, h - 1) * ish;
 #pragma unroll
-                    for (int kb = 0; kb < KB; ++kb)
-                        if (cv[kb]) v[rb][kb] = rp[coff[kb]];
-                }
-            }
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const int ty = t0 + rb * kWaves;
-                if (ty < rows) {
-                    TS* trow = tile + ty * TP + k0 + lane;
-#pragma unroll
-                    for (int kb = 0; kb < KB; ++kb)
-                        if (cv[kb]) trow[kb * 64] = to_stage<TS, TIn>(v[rb][kb]);
-                }
+                for (int kb = 0; kb < KB; ++kb)
+                    if (cv[kb]) v[rb][kb] = rp[coff[kb]];
             }
         }
     }
-}
+    __device__ __forceinline__ void commit(TS* tile, int TP) {
+        const int wave = wave_id(), lane = threadIdx.x & 63;
+#pragma unroll
+        for (int rb = 0; rb < kRowsPerWave; ++rb) {
+            const int ty = wave + rb * (kThreads / 64);
+            if (ty < rows) {
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    if (cv[kb]) tile[ty * TP + kb * 64 + lane] = to_stage<TS, TIn>(v[rb][kb]);
+            }
+        }
+        for (int k0 = 64 * KB; k0 < TW; k0 += 64) {
+            const int tx = k0 + lane;
+            if (tx >= TW) continue;
+            const uint32_t co = (uint32_t)clampi(x_first + tx, 0, w - 1) * (uint32_t)isw;
+            for (int ty = wave; ty < rows; ty += kThreads / 64)
+                tile[ty * TP + tx] = to_stage<TS, TIn>(plane[(int64_t)clampi(y0 + ty, 0, h - 1) * ish + co]);
+        }
+    }
+};
 
 // 8-bit input staged as exact fp16, two columns per lane and one 32-bit LDS
 // write per pair: the bytes b0, b1 are placed under the fp16 exponent of 1024
 // (bits 0x6400 | b encode 1024 + b exactly) and 1024 is subtracted from both
-// halves at once.
+// halves at once.  One 128-column chunk is prefetched.
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
-template <>
-__device__ __forceinline__ void stage_rows<uint8_t, _Float16>(_Float16* tile, int TP, const uint8_t* plane,
-                                                             int64_t ish, int64_t isw, int y_first, int x_first,
-                                                             int s0, int rows, int TW, int h, int w) {
-    constexpr int RB = 8, kWaves = kThreads / 64;
-    const int wave = wave_id(), lane = threadIdx.x & 63;
+__device__ __forceinline__ half2_t bytes_to_half2(uint32_t b0, uint32_t b1) {
     const half2_t bias = {(_Float16)1024.0f, (_Float16)1024.0f};
-    for (int k0 = 0; k0 < TW; k0 += 128) {
-        const int tx = k0 + 2 * lane;  // this lane's first column; tx + 1 < TP always
-        const bool cv = tx < TW;
-        const uint32_t c0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * (uint32_t)isw;
-        const uint32_t c1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * (uint32_t)isw;
-        for (int t0 = wave; t0 < rows; t0 += kWaves * RB) {
-            uint32_t b0[RB], b1[RB];
+    const uint32_t bits = (b1 << 16) | b0 | 0x64006400u;
+    return __builtin_bit_cast(half2_t, bits) - bias;
+}
+
+template <>
+struct Stager<uint8_t, _Float16> {
+    uint32_t b0[kRowsPerWave], b1[kRowsPerWave];
+    uint32_t c0, c1;
+    bool cv;
+    const uint8_t* plane;
+    int64_t ish, isw;
+    int y0, rows, h, w, x_first, TW;
+
+    __device__ __forceinline__ void setup(int x_first_, int TW_, int w_, int64_t isw_, int64_t ish_, int h_) {
+        x_first = x_first_; TW = TW_; w = w_; isw = isw_; ish = ish_; h = h_;
+        const int tx = 2 * (threadIdx.x & 63);  // tx + 1 < TP always
+        cv = tx < TW;
+        c0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * (uint32_t)isw;
+        c1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * (uint32_t)isw;
+    }
+    __device__ __forceinline__ void issue(const uint8_t* plane_, int y0_, int rows_) {
+        plane = plane_; y0 = y0_; rows = rows_;
+        const int wave = wave_id();
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const int ty = t0 + rb * kWaves;
-                if (ty < rows && cv) {
-                    const uint8_t* rp = plane + (int64_t)clampi(y_first + s0 + ty, 0, h - 1) * ish;
-                    b0[rb] = rp[c0];
-                    b1[rb] = rp[c1];
-                }
-            }
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const int ty = t0 + rb * kWaves;
-                if (ty < rows && cv) {
-                    const uint32_t bits = (b1[rb] << 16) | b0[rb] | 0x64006400u;
-                    const half2_t hv = __builtin_bit_cast(half2_t, bits) - bias;
-                    *reinterpret_cast<half2_t*>(tile + ty * TP + tx) = hv;
-                }
+        for (int rb = 0; rb < kRowsPerWave; ++rb) {
+            const int ty = wave + rb * (kThreads / 64);
+            if (ty < rows && cv) {
+                const uint8_t* rp = plane + (int64_t)clampi(y0 + ty, 0, h - 1) * ish;
+                b0[rb] = rp[c0];
+                b1[rb] = rp[c1];
             }
         }
     }
-}
-
-struct FragLoc {
-    int f, lb, bx, by, xa, ya, bw, bh;
+    __device__ __forceinline__ void commit(_Float16* tile, int TP) {
+        const int wave = wave_id(), lane = threadIdx.x & 63;
+#pragma unroll
+        for (int rb = 0; rb < kRowsPerWave; ++rb) {
+            const int ty = wave + rb * (kThreads / 64);
+            if (ty < rows && cv)
+                *reinterpret_cast<half2_t*>(tile + ty * TP + 2 * lane) = bytes_to_half2(b0[rb], b1[rb]);
+        }
+        for (int k0 = 128; k0 < TW; k0 += 128) {
+            const int tx = k0 + 2 * lane;
+            if (tx >= TW) continue;
+            const uint32_t d0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * (uint32_t)isw;
+            const uint32_t d1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * (uint32_t)isw;
+            for (int ty = wave; ty < rows; ty += kThreads / 64) {
+                const uint8_t* rp = plane + (int64_t)clampi(y0 + ty, 0, h - 1) * ish;
+                *reinterpret_cast<half2_t*>(tile + ty * TP + tx) = bytes_to_half2(rp[d0], rp[d1]);
+            }
+        }
+    }
 };
 
-__device__ __forceinline__ FragLoc locate(const FwdLaunch& a, int gid) {
-    FragLoc L;
-    int f = 0;
-    while (f + 1 < a.nframes && gid >= a.blk_prefix[f + 1]) ++f;
-    const FrameParams& fp = a.fr[f];
-    L.f = f;
-    L.lb = gid - a.blk_prefix[f];
-    L.by = L.lb / fp.nbx;
-    L.bx = L.lb - L.by * fp.nbx;
-    const int B = fp.block;
-    const int X0 = fp.origin_x + L.bx * B, Y0 = fp.origin_y + L.by * B;
-    L.xa = max(X0, 0);
-    L.ya = max(Y0, 0);
-    L.bw = min(X0 + B, a.w) - L.xa;
-    L.bh = min(Y0 + B, a.h) - L.ya;
-    return L;
+// ---- fragments of a launch ---------------------------------------------------------------------
+// Last frame whose first fragment is <= gid (prefix has nframes+1 entries).
+__device__ __forceinline__ int frame_search(const int32_t* __restrict__ prefix, int nframes, int gid) {
+    int lo = 0, hi = nframes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= gid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
-template <typename TIn, typename TOut, typename TS, typename TC>
-__global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, const int32_t* __restrict__ radius,
-                                                           const TC* __restrict__ wts,
-                                                           const int32_t* __restrict__ order) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int gid = order[blockIdx.x];
-    const FragLoc L = locate(a, gid);
-    const TIn* in = static_cast<const TIn*>(a.in.data) + (int64_t)(a.frame_base + L.f) * a.in.sn;
-    TOut* out = static_cast<TOut*>(a.out.data) + (int64_t)(a.frame_base + L.f) * a.out.sn;
-    const int r = radius[gid];
-    const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63;
-    constexpr int kWaves = kThreads / 64;
+// Everything the kernels need to know about one fragment.
+struct Frag {
+    const FrameDesc* fd;
+    int lb, bx, by, xa, ya, bw, bh;
+};
 
-    if (r == 0) {  // foveal fragment: copied (Appendix "Workload of the Block")
-        for (int c = 0; c < a.c; ++c)
-            for (int y = wave; y < L.bh; y += kWaves)
-                for (int x = lane; x < L.bw; x += 64) {
-                    const TIn v = in[c * a.in.sc + (int64_t)(L.ya + y) * a.in.sh + (int64_t)(L.xa + x) * a.in.sw];
-                    out[c * a.out.sc + (int64_t)(L.ya + y) * a.out.sh + (int64_t)(L.xa + x) * a.out.sw] =
-                        copy_out<TOut, TIn>(v);
-                }
+__device__ __forceinline__ Frag describe_at(const FrameDesc* fd, int first, int gid) {
+    Frag F;
+    F.fd = fd;
+    const FrameParams& fp = fd->p;
+    F.lb = gid - first;
+    F.by = F.lb / fp.nbx;
+    F.bx = F.lb - F.by * fp.nbx;
+    const int B = fp.block;
+    const int X0 = fp.origin_x + F.bx * B, Y0 = fp.origin_y + F.by * B;
+    F.xa = max(X0, 0);
+    F.ya = max(Y0, 0);
+    F.bw = min(X0 + B, fd->w) - F.xa;
+    F.bh = min(Y0 + B, fd->h) - F.ya;
+    return F;
+}
+
+// Fragment gid, reading frames from the device table (main kernel).
+__device__ __forceinline__ Frag describe(const FrameDesc* __restrict__ table, const int32_t* __restrict__ prefix,
+                                         int nframes, int gid) {
+    const int f = frame_search(prefix, nframes, gid);
+    return describe_at(table + f, prefix[f], gid);
+}
+
+// Foveal fragment: copied (Appendix "Workload of the Block").
+template <typename TIn, typename TOut>
+__device__ __forceinline__ void copy_fragment(const Frag& F) {
+    const FrameDesc& d = *F.fd;
+    const TIn* in = static_cast<const TIn*>(d.in);
+    TOut* out = static_cast<TOut*>(d.out);
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    for (int c = 0; c < d.c; ++c)
+        for (int y = wave; y < F.bh; y += kThreads / 64)
+            for (int x = lane; x < F.bw; x += 64) {
+                const TIn v = in[c * d.isc + (int64_t)(F.ya + y) * d.ish + (int64_t)(F.xa + x) * d.isw];
+                out[c * d.osc + (int64_t)(F.ya + y) * d.osh + (int64_t)(F.xa + x) * d.osw] = copy_out<TOut, TIn>(v);
+            }
+}
+
+// ---- main kernel ---------------------------------------------------------------------------------
+// One fragment: stage its padded tile strip by strip (the next strip's loads
+// in flight while the current one is computed), horizontal pass into the
+// column-major intermediate, vertical pass into the output.
+template <typename TIn, typename TOut, typename TS, typename TC>
+__device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, int r, const Frag& F,
+                                                 const TC* __restrict__ wts, unsigned char* smem) {
+    const FrameDesc& d = *F.fd;
+    if (r == 0) {
+        copy_fragment<TIn, TOut>(F);
         return;
     }
-
+    const int tid = threadIdx.x;
     const TC* __restrict__ w = wts + (size_t)gid * a.wstride;
-    const Geom g = geom(r, L.bw, L.bh);
-    const int SR = min(a.strip_rows, g.TH);
+    const Geom g = geom(r, F.bw, F.bh);
+    const int SR = min(min(a.strip_rows, kStripMax), g.TH);
     const int TP = tile_pitch(g.TW, sizeof(TS));
-    TS* tile = reinterpret_cast<TS*>(smem);
     const int IP = inter_pitch(g.TH, sizeof(TC));
+    TS* tile = reinterpret_cast<TS*>(smem);
     TC* inter = reinterpret_cast<TC*>(smem + align16((size_t)SR * TP * sizeof(TS)));  // [column][row]
-
-    for (int c = 0; c < a.c; ++c) {
-        const TIn* plane = in + c * a.in.sc;
-        for (int s0 = 0; s0 < g.TH; s0 += SR) {
-            const int rows = min(SR, g.TH - s0);
-            if (s0 > 0) __syncthreads();  // every thread is done reading the previous strip
-            stage_rows<TIn, TS>(tile, TP, plane, a.in.sh, a.in.sw, L.ya - r, L.xa - r, s0, rows, g.TW, a.h, a.w);
-            __syncthreads();
-            // Task t: lanes of a 16-lane group take 16 consecutive rows of one
-            // column group, so 16-byte row reads from LDS are conflict-free.
-            const int ntask = round_up(rows, 16) * g.G;
-            for (int t = tid; t < ntask; t += kThreads) {
-                const int blk = t >> 4, gi = blk % g.G;
-                const int ty = ((blk / g.G) << 4) | (t & 15), x0 = gi * kPH;
-                if (ty >= rows) continue;
-                TC acc[kPH];
+    const TIn* in = static_cast<const TIn*>(d.in);
+    TOut* out = static_cast<TOut*>(d.out);
+    const int nst = (g.TH + SR - 1) / SR;
+    const int nunits = d.c * nst;
+    Stager<TIn, TS> st;
+    st.setup(F.xa - r, g.TW, d.w, d.isw, d.ish, d.h);
+    st.issue(in, F.ya - r, SR);
+    st.commit(tile, TP);
+    __syncthreads();
+    for (int u = 0; u < nunits; ++u) {
+        const int c = u / nst, sidx = u - c * nst;
+        const int s0 = sidx * SR, rows = min(SR, g.TH - s0);
+        if (u + 1 < nunits) {
+            const int cn = (u + 1) / nst, sn = (u + 1) - cn * nst;
+            st.issue(in + cn * d.isc, F.ya - r + sn * SR, min(SR, g.TH - sn * SR));
+        }
+        // Horizontal pass.  Task t: lanes of a 16-lane group take 16
+        // consecutive rows of one column group (conflict-free row reads).
+        const int ntask = round_up(rows, 16) * g.G;
+        for (int t = tid; t < ntask; t += kThreads) {
+            const int blk = t >> 4, gi = blk % g.G;
+            const int ty = ((blk / g.G) << 4) | (t & 15), x0 = gi * kPH;
+            if (ty >= rows) continue;
+            TC acc[kPH];
 #pragma unroll
-                for (int p = 0; p < kPH; ++p) acc[p] = 0;
-                hconv(acc, tile + ty * TP + x0, g.N, w);
-                TC* dst = inter + x0 * IP + s0 + ty;
+            for (int p = 0; p < kPH; ++p) acc[p] = 0;
+            hconv(acc, tile + ty * TP + x0, g.N, w);
+            TC* dst = inter + x0 * IP + s0 + ty;
 #pragma unroll
-                for (int p = 0; p < kPH; ++p) dst[p * IP] = acc[p];
+            for (int p = 0; p < kPH; ++p) dst[p * IP] = acc[p];
+        }
+        __syncthreads();  // the tile is free; the channel's intermediate may be complete
+        if (sidx == nst - 1) {
+            // Vertical pass over the complete intermediate of channel c.
+            TOut* oc = out + c * d.osc;
+            for (int t = tid; t < F.bw * g.GV; t += kThreads) {
+                const int gv = t / F.bw, x = t - gv * F.bw, y0 = gv * kPV;
+                TC acc[kPV];
+#pragma unroll
+                for (int p = 0; p < kPV; ++p) acc[p] = 0;
+                vconv(acc, inter + x * IP + y0, g.N, w);
+                TOut* o = oc + (int64_t)(F.xa + x) * d.osw;
+#pragma unroll
+                for (int p = 0; p < kPV; ++p)
+                    if (y0 + p < F.bh) o[(int64_t)(F.ya + y0 + p) * d.osh] = to_out<TOut, TC>(acc[p]);
             }
         }
-        __syncthreads();
-        TOut* oc = out + c * a.out.sc;
-        for (int t = tid; t < L.bw * g.GV; t += kThreads) {
-            const int gv = t / L.bw, x = t - gv * L.bw, y0 = gv * kPV;
-            TC acc[kPV];
-#pragma unroll
-            for (int p = 0; p < kPV; ++p) acc[p] = 0;
-            vconv(acc, inter + x * IP + y0, g.N, w);
-            TOut* o = oc + (int64_t)(L.xa + x) * a.out.sw;
-#pragma unroll
-            for (int p = 0; p < kPV; ++p)
-                if (y0 + p < L.bh) o[(int64_t)(L.ya + y0 + p) * a.out.sh] = to_out<TOut, TC>(acc[p]);
+        if (u + 1 < nunits) {
+            st.commit(tile, TP);
+            __syncthreads();  // next strip staged; every thread is past the previous vertical pass
         }
     }
 }
 
+// Fragments are taken from the queue (fragment ids by decreasing radius, so
+// the costliest start first).  PERSIST = false: one workgroup per queue slot,
+// the hardware dispatcher hands slots out in order as workgroups retire.
+// PERSIST = true: a grid sized to what the chip holds at once; workgroup b
+// takes slots b, b + grid, b + 2 grid, ... (round-robin over the cost-sorted
+// queue balances the load without atomics).
+template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
+__global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, const int32_t* __restrict__ radius,
+                                                           const TC* __restrict__ wts,
+                                                           const int32_t* __restrict__ order,
+                                                           const FrameDesc* __restrict__ table,
+                                                           const int32_t* __restrict__ prefix) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (int q = blockIdx.x; q < a.nfrag; q += gridDim.x) {
+        const int gid = order[q];
+        const int r = radius[gid];
+        const Frag F = describe(table, prefix, a.nframes, gid);
+        process_fragment<TIn, TOut, TS, TC>(a, gid, r, F, wts, smem);
+        if (!PERSIST) break;
+        __syncthreads();  // this fragment's LDS reads are done before the next one is staged
+    }
+}
+
+// ---- plan kernels --------------------------------------------------------------------------------
 // Fragment plan: radius and normalised taps, one wavefront per fragment.
 template <typename TC>
 __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a, int32_t* __restrict__ radius,
                                                               TC* __restrict__ wts) {
     const int gid = blockIdx.x;
-    const FragLoc L = locate(a, gid);
-    const FrameParams& fp = a.fr[L.f];
-    const double sigma = fp.sigma_map ? clip_map_sigma((double)fp.sigma_map[L.lb], fp.cap)
-                                      : fragment_sigma_ramp(fp, L.bx, L.by);
+    const int lane = threadIdx.x;
+    Frag F;
+    if (a.from_args) {
+        int f = 0;
+        while (f + 1 < a.nframes && gid >= a.kprefix[f + 1]) ++f;
+        F = describe_at(&a.fr[f], a.kprefix[f], gid);
+        if (gid == 0) {
+            // publish the frame table for the main kernel
+            constexpr int kWords = sizeof(FrameDesc) / 4;
+            const int32_t* src = reinterpret_cast<const int32_t*>(a.fr);
+            int32_t* dst = reinterpret_cast<int32_t*>(a.table);
+            for (int i = lane; i < a.nframes * kWords; i += 64) dst[i] = src[i];
+            for (int i = lane; i <= a.nframes; i += 64) a.prefix[i] = a.kprefix[i];
+        }
+    } else {
+        F = describe(a.table, a.prefix, a.nframes, gid);
+    }
+    const FrameParams& fp = F.fd->p;
+    const double sigma = fp.sigma_map ? clip_map_sigma((double)fp.sigma_map[F.lb], fp.cap)
+                                      : fragment_sigma_ramp(fp, F.bx, F.by);
     int r = radius_of(sigma);
     if (r > a.r_cap) r = a.r_cap;  // the host sized everything for r_cap; plans agree bit for bit
-    const int lane = threadIdx.x;
     if (lane == 0) radius[gid] = r;
     const int N = 2 * r + 1;
     const double inv = r > 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
     constexpr int kHeld = 4;  // taps per lane kept in registers
-    double g[kHeld];
+    double gv[kHeld];
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < kHeld; ++q) {
         const int j = lane + 64 * q;
         const double k = (double)(j - r);
-        g[q] = j < N ? exp(-(k * k) * inv) : 0.0;
-        part += g[q];
+        gv[q] = j < N ? exp(-(k * k) * inv) : 0.0;
+        part += gv[q];
     }
     for (int j = lane + 64 * kHeld; j < N; j += 64) {
         const double k = (double)(j - r);
@@ -447,7 +565,7 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
 #pragma unroll
     for (int q = 0; q < kHeld; ++q) {
         const int j = lane + 64 * q;
-        if (j < a.wstride) wr[j] = (TC)(g[q] / part);
+        if (j < a.wstride) wr[j] = (TC)(gv[q] / part);
     }
     for (int j = lane + 64 * kHeld; j < a.wstride; j += 64) {
         double v = 0.0;
@@ -459,10 +577,10 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
     }
 }
 
-// Dispatch order: fragments by decreasing radius (their cost grows with r),
-// so the costliest start first and the launch does not end on a long tail.
-// One workgroup: LDS histogram of radii, exclusive scan from the top, scatter.
-// The order among equal radii is arbitrary; results do not depend on it.
+// Queue order: fragments by decreasing radius (their cost grows with r), so
+// the costliest start first and the launch does not end on a long tail.  One
+// workgroup: LDS histogram of radii, exclusive scan from the top, scatter; the
+// order among equal radii is arbitrary and results do not depend on it.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = 1024;
 
@@ -506,35 +624,66 @@ __global__ void fov_plan_kernel(FrameParams fp, int n, double* sigma_out, int32_
     r_out[b] = radius_of(s);
 }
 
-template <typename TIn, typename TOut, typename TS, typename TC>
+template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
 struct FwdSlot {
     static bool configured;
+    static size_t occ_lds;
+    static int occ_blocks;
 };
-template <typename TIn, typename TOut, typename TS, typename TC>
-bool FwdSlot<TIn, TOut, TS, TC>::configured = false;
+template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
+bool FwdSlot<TIn, TOut, TS, TC, PERSIST>::configured = false;
+template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
+size_t FwdSlot<TIn, TOut, TS, TC, PERSIST>::occ_lds = 0;
+template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
+int FwdSlot<TIn, TOut, TS, TC, PERSIST>::occ_blocks = 0;
 
-template <typename TIn, typename TOut, typename TS, typename TC>
-fov_status launch_typed(const FwdLaunch& a, int nblocks, size_t lds, const PlanBuffers& plan, hipStream_t stream,
-                        size_t lds_limit) {
-    TC* wts = static_cast<TC*>(plan.weights);
-    hipLaunchKernelGGL(fov_plan_weights_kernel<TC>, dim3(nblocks), dim3(64), 0, stream, a, plan.radius, wts);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_error(e, "plan kernel launch");
-    hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.radius,
-                       nblocks, std::min(a.r_cap + 1, kOrderBins), plan.order);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_error(e, "order kernel launch");
-    auto kern = fov_fwd_kernel<TIn, TOut, TS, TC>;
-    if (!FwdSlot<TIn, TOut, TS, TC>::configured) {
-        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
+template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
+fov_status launch_main(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, hipStream_t stream,
+                       size_t lds_limit, int cus) {
+    using Slot = FwdSlot<TIn, TOut, TS, TC, PERSIST>;
+    auto kern = fov_fwd_kernel<TIn, TOut, TS, TC, PERSIST>;
+    hipError_t e;
+    if (!Slot::configured) {
+        hipFuncAttributes fa;
+        e = hipFuncGetAttributes(&fa, (const void*)kern);
+        if (e != hipSuccess) return hip_error(e, "hipFuncGetAttributes(forward)");
+        const size_t dyn_max = lds_limit > fa.sharedSizeBytes ? lds_limit - fa.sharedSizeBytes : 0;
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max);
         if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(forward)");
-        FwdSlot<TIn, TOut, TS, TC>::configured = true;
+        Slot::configured = true;
     }
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreads), lds, stream, a, (const int32_t*)plan.radius,
-                       (const TC*)wts, (const int32_t*)plan.order);
+    int grid = a.nfrag;
+    if (PERSIST) {
+        if (Slot::occ_lds != lds) {
+            int nb = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)kern, kThreads, lds);
+            if (e != hipSuccess) return hip_error(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+            Slot::occ_blocks = std::max(nb, 1);
+            Slot::occ_lds = lds;
+        }
+        grid = std::max(1, std::min(a.nfrag, Slot::occ_blocks * cus));
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, stream, a, (const int32_t*)plan.radius,
+                       (const TC*)plan.weights, (const int32_t*)plan.order, (const FrameDesc*)a.table,
+                       (const int32_t*)a.prefix);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "forward kernel launch");
     return FOV_OK;
+}
+
+template <typename TIn, typename TOut, typename TS, typename TC>
+fov_status launch_typed(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, hipStream_t stream,
+                        size_t lds_limit, int cus, bool persist) {
+    TC* wts = static_cast<TC*>(plan.weights);
+    hipLaunchKernelGGL(fov_plan_weights_kernel<TC>, dim3(a.nfrag), dim3(64), 0, stream, a, plan.radius, wts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "plan kernel launch");
+    hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.radius,
+                       a.nfrag, std::min(a.r_cap + 1, kOrderBins), plan.order);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "order kernel launch");
+    if (persist) return launch_main<TIn, TOut, TS, TC, true>(a, lds, plan, stream, lds_limit, cus);
+    return launch_main<TIn, TOut, TS, TC, false>(a, lds, plan, stream, lds_limit, cus);
 }
 
 int stage_size(int in_dtype) { return in_dtype == FOV_U8 ? 2 : (in_dtype == FOV_F32 ? 4 : 8); }
@@ -543,36 +692,41 @@ int compute_size(int in_dtype) { return in_dtype == FOV_F64 ? 8 : 4; }
 }  // namespace
 
 size_t plan_bytes(int nfrag, int wstride, int wsize) {
-    return 2 * align16((size_t)nfrag * 4) + (size_t)nfrag * wstride * wsize;
+    return 2 * align16((size_t)nfrag * 4) + 256 + (size_t)nfrag * wstride * wsize;
 }
 
-PlanBuffers carve_plan(void* ws, int nfrag) {
+PlanBuffers carve_plan(void* ws, int nfrag, int wstride, int wsize) {
+    (void)wstride;
+    (void)wsize;
     PlanBuffers p;
     char* base = static_cast<char*>(ws);
     p.radius = reinterpret_cast<int32_t*>(base);
     p.order = reinterpret_cast<int32_t*>(base + align16((size_t)nfrag * 4));
-    p.weights = base + 2 * align16((size_t)nfrag * 4);
+    p.weights = base + 2 * align16((size_t)nfrag * 4) + 256;
     return p;
 }
 
+int forward_strip_max() { return kStripMax; }
+
 size_t forward_lds_bytes(int in_dtype, int r_cap, int B, int strip_rows) {
     const Geom g = geom(r_cap, B, B);
-    const int rows = strip_rows < g.TH ? strip_rows : g.TH;
+    int rows = strip_rows < g.TH ? strip_rows : g.TH;
+    if (rows > kStripMax) rows = kStripMax;
     const int es = stage_size(in_dtype), ec = compute_size(in_dtype);
     return align16((size_t)rows * tile_pitch(g.TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec + 64;
 }
 
-fov_status launch_forward(const FwdLaunch& a, int nblocks, int in_dtype, int out_dtype, size_t lds,
-                          const PlanBuffers& plan, hipStream_t stream, size_t lds_limit) {
-    if (nblocks <= 0) return FOV_OK;
+fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,
+                          hipStream_t stream, size_t lds_limit, int cus, bool persist) {
+    if (a.nfrag <= 0) return FOV_OK;
     if (in_dtype == FOV_U8 && out_dtype == FOV_U8)
-        return launch_typed<uint8_t, uint8_t, _Float16, float>(a, nblocks, lds, plan, stream, lds_limit);
+        return launch_typed<uint8_t, uint8_t, _Float16, float>(a, lds, plan, stream, lds_limit, cus, persist);
     if (in_dtype == FOV_U8 && out_dtype == FOV_F32)
-        return launch_typed<uint8_t, float, _Float16, float>(a, nblocks, lds, plan, stream, lds_limit);
+        return launch_typed<uint8_t, float, _Float16, float>(a, lds, plan, stream, lds_limit, cus, persist);
     if (in_dtype == FOV_F32 && out_dtype == FOV_F32)
-        return launch_typed<float, float, float, float>(a, nblocks, lds, plan, stream, lds_limit);
+        return launch_typed<float, float, float, float>(a, lds, plan, stream, lds_limit, cus, persist);
     if (in_dtype == FOV_F64 && out_dtype == FOV_F64)
-        return launch_typed<double, double, double, double>(a, nblocks, lds, plan, stream, lds_limit);
+        return launch_typed<double, double, double, double>(a, lds, plan, stream, lds_limit, cus, persist);
     return set_error(FOV_EDTYPE, "unsupported dtype pair");
 }
 
