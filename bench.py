@@ -15,9 +15,11 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -53,23 +55,77 @@ def algorithmic_fma(h, w, c, p, plan_r):
     return total
 
 
-def cpu_baseline(frame, p, target_s=10.0):
-    """FP64 oracle (all host threads) on a random pixel sample of one frame."""
+KERNEL_SOURCES = ("paper_2012_08655_amd/csrc/forward.hip", "paper_2012_08655_amd/csrc/forward.h",
+                  "paper_2012_08655_amd/csrc/common.h")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fov_fwd_u8_1080p_rgb_traffic.md")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the forward kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when the summary is missing or the kernel sources
+    changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^- (\w+): ([0-9a-f.]+)\s*$", text, re.M))
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mb, reps):
+    """A plain device-to-device copy of a known size, for scaling the PMC
+    byte counters (profile it with --pmc FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    n = mb * (1 << 20)
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_dispatch": n, "reps": reps}))
+
+
+def cpu_baseline(frame, rng_seed=99, target_s=10.0):
+    """FP64 oracle (all host threads) on whole frames of the same workload
+    (fresh central-half fixation per frame) until target_s seconds of CPU work
+    have run; the last frame may be a random pixel subset to bound the time."""
     import oracle
+    import synth
     oracle.build(force=False)
     x = frame.transpose(2, 0, 1).astype(np.float64)
-    rng = np.random.default_rng(99)
-    npts = 2000
-    while True:
-        ys, xs = rng.integers(0, H, npts), rng.integers(0, W, npts)
+    rng = np.random.default_rng(rng_seed)
+    done_px, spent, frames = 0, 0.0, 0
+    while spent < target_s:
+        p = synth.params_cfg2(rng)
+        left = target_s - spent
+        per_px = spent / done_px if done_px else None
+        if per_px is None:
+            npts = 100000  # calibration sample
+        else:
+            npts = H * W if per_px * H * W <= left else max(1000, int(left / per_px))
+        ys, xs = np.divmod(rng.permutation(H * W)[:npts], W)
         t0 = time.perf_counter()
         oracle.forward_points(x, p, ys, xs)
-        dt = time.perf_counter() - t0
-        if dt >= target_s or npts >= H * W:
-            break
-        npts = int(min(H * W, npts * max(2.0, 1.1 * target_s / max(dt, 1e-3))))
-    return {"value": npts / dt / 1e6, "unit": "Mpix/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": "%d random pixels (x3 channels) of one 1920x1080 RGB frame, FP64 direct 2-D, %.1f s" % (npts, dt)}
+        spent += time.perf_counter() - t0
+        done_px += npts
+        frames += 1
+    return {"value": done_px / spent / 1e6, "unit": "Mpix/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "%d pixels (x3 channels) over %d 1920x1080 RGB frames with random central-half fixations, "
+                      "FP64 direct 2-D, %.1f s" % (done_px, frames, spent)}
 
 
 def main():
@@ -81,7 +137,12 @@ def main():
     ap.add_argument("--distinct", type=int, default=4, help="distinct frame contents in the pool")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain MB-sized device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, 5)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method needs no communication and this build "
               "runs on a single MI355X (frames shard trivially across GPUs)", file=sys.stderr)
@@ -116,7 +177,10 @@ def main():
 
     # Timed region: exactly `steps` frames, with per-launch HIP events on the
     # launch stream.
+    # The library records events around each main kernel (plan and order
+    # kernels excluded); torch events bracket each whole call.
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    fov.profile_begin(args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for j in range(args.steps):
@@ -126,7 +190,9 @@ def main():
         ev[j][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms = np.array([a.elapsed_time(b) for a, b in ev])
+    kms = fov.profile_end(args.steps)
+    call_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    assert len(kms) == args.steps
     print("bench: timed %d steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
 
     mpix = H * W / 1e6
@@ -141,6 +207,7 @@ def main():
     achieved_tflops = float(np.mean(flops / (kms * 1e-3)) / 1e12)
     bytes_per_frame = H * W * C * 2
     achieved_gbs = float(bytes_per_frame / (kms.mean() * 1e-3) / 1e9)
+    traffic = measured_traffic()
 
     result = {
         "metric": METRIC,
@@ -158,12 +225,13 @@ def main():
         "config": {"workload": "1920x1080 RGB u8 -> u8, 32x32 fragments, sigma = 0.02*(e-64) capped at 16, "
                                "radius ceil(3 sigma), clamp-to-edge, one frame per launch",
                    "frame_pixels": H * W, "channels": C, "block": 32},
-        "frame_latency_ms": {"p50": round(float(np.percentile(kms, 50)), 5),
-                             "p99": round(float(np.percentile(kms, 99)), 5),
-                             "kind": "plain per-frame launch, kernel time (HIP events)"},
+        "frame_latency_ms": {"p50": round(float(np.percentile(call_ms, 50)), 5),
+                             "p99": round(float(np.percentile(call_ms, 99)), 5),
+                             "kind": "plain per-frame launch: device time of one call (plan, order and main "
+                                     "kernels), HIP events"},
         "roofline": {"bound": "alu", "kernel": "fov_fwd_kernel<u8,u8,f32>",
                      "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                      "algorithmic_flops_per_launch": float(np.mean(flops)),
                      "mean_launch_ms": round(float(kms.mean()), 5),
                      "hbm_GBs_algorithmic": round(achieved_gbs, 1)},
@@ -171,7 +239,7 @@ def main():
     }
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(distinct[0], params[args.warmup])
+        result["cpu_baseline"] = cpu_baseline(distinct[0], target_s=args.cpu_seconds)
     print(json.dumps(result))
 
 

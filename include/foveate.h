@@ -154,6 +154,92 @@ fov_status foveate_forward_batch(const fov_tensor* ins, const fov_tensor* outs, 
 fov_status foveate_backward(const fov_tensor* grad_out, const fov_tensor* grad_in,
                             const fov_params* p, int32_t np, void* stream);
 
+/* ---- serving -------------------------------------------------------------------------------
+ *
+ * A request loop for frames that arrive one at a time (each with its own
+ * size and gaze), in the spirit of the paper's per-frame asynchronous loop
+ * (Alg. 1, "with every frame"), with continuous batching: a scheduler thread
+ * admits queued frames while the bytes of admitted, unfinished frames stay
+ * within an HBM budget, launches everything admitted as one batched forward
+ * (the queue of foveate_forward_batch) on one of several streams, and admits
+ * and launches frames that arrive while other batches are on the device, so
+ * consecutive batches overlap on the GPU.  Frames stay where the caller put
+ * them (device memory); results are identical to foveate_forward's.
+ */
+typedef struct fov_server fov_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;      /* inputs + outputs of admitted, unfinished frames (> 0)      */
+    int32_t max_batch_frames;     /* frames per batch, 1..4096                                  */
+    int32_t max_inflight_batches; /* batches on the device at once, 1..8 (one stream each)      */
+    int32_t max_requests;         /* request table size: queued + in flight + done, not polled  */
+    int32_t in_dtype, out_dtype;  /* the one dtype pair this server serves (as forward)         */
+    int32_t max_fragments;        /* fragments per batch (sizes the plan workspace)             */
+    int32_t max_block;            /* largest fragment side a request may use (1..64)            */
+    double max_sigma;             /* largest sigma a request may produce (sizes LDS and taps)   */
+    int32_t use_graph;            /* 1: every batch replays a hipGraph captured at creation     */
+    int32_t test_fake_device_us;  /* test hook: > 0 launches no kernels and completes each
+                                     batch after this many microseconds (outputs untouched)     */
+    int32_t test_fail_every;      /* test hook: every k-th batch completes with FOV_EHIP        */
+    int32_t reserved;             /* must be 0                                                  */
+} fov_server_cfg;
+
+typedef struct {
+    double t_submit, t_admit, t_launch, t_done; /* foveate_now() clock, seconds            */
+    int32_t batch_frames;                        /* frames in the batch this one ran in     */
+    int32_t status;                              /* fov_status of the frame's batch         */
+} fov_timing;
+
+/* Monotonic host clock (seconds) used for every server timestamp. */
+double foveate_now(void);
+
+/*
+ * Create a server on the current device: streams, the scheduler thread and,
+ * with use_graph, one captured batch graph per stream with its own workspace
+ * (allocated here, sized by max_batch_frames, max_fragments, max_block and
+ * max_sigma).  FOV_EINVAL for bad configuration, FOV_ENOMEM, FOV_EHIP.
+ */
+fov_status foveate_server_create(const fov_server_cfg* cfg, fov_server** out);
+
+/*
+ * Queue one frame: in, out are single-frame views (n == 1) of the server's
+ * dtype pair; p its parameters (block <= max_block, every fragment's sigma
+ * <= max_sigma, at most max_fragments fragments).  The buffers (and a sigma
+ * map, if any) must stay alive until poll reports the ticket done.  Returns
+ * immediately with *ticket.  FOV_EAGAIN: request table full (poll and retry);
+ * FOV_ECLOSED: the server is being destroyed; FOV_EINVAL / FOV_ERANGE /
+ * FOV_EDTYPE / FOV_EALIAS as for forward, or a frame larger than the budget.
+ */
+fov_status foveate_submit(fov_server* s, const fov_tensor* in, const fov_tensor* out, const fov_params* p,
+                          uint64_t* ticket);
+
+/*
+ * *done = 1 once the frame's output is complete (then the ticket is retired
+ * and *t, if not NULL, holds its timestamps), else 0.  Returns the frame's
+ * status when done (FOV_OK, or the error its batch hit), FOV_OK while
+ * pending, FOV_ENOTICKET for an unknown or retired ticket.
+ */
+fov_status foveate_poll(fov_server* s, uint64_t ticket, int32_t* done, fov_timing* t);
+
+/* Block until every queued frame is done; tickets stay pollable. */
+fov_status foveate_server_drain(fov_server* s);
+
+/* Finish all queued work, stop the scheduler, release everything. */
+fov_status foveate_server_destroy(fov_server* s);
+
+/*
+ * Kernel timing for measurement.  Between foveate_profile_begin(capacity) and
+ * foveate_profile_end(), each forward call made by this thread records a pair
+ * of HIP events on its stream right before and right after its main kernel
+ * (the per-fragment blur; the plan and order kernels that precede it are not
+ * included), up to `capacity` calls.  foveate_profile_end waits for the
+ * recorded events, writes up to `capacity` durations in milliseconds to ms
+ * (host array, may be NULL), stores how many in *count and releases the
+ * events.  FOV_EINVAL if profiling was not started.
+ */
+fov_status foveate_profile_begin(int32_t capacity);
+fov_status foveate_profile_end(float* ms, int32_t capacity, int32_t* count);
+
 /* Thread-local message for the last non-OK status of this thread ("" if none). */
 const char* foveate_last_error(void);
 

@@ -18,7 +18,7 @@ def __getattr__(name):
     # The torch binding is imported lazily so that loading the C library (and
     # checking its exports) does not require torch.
     if name in ("forward", "forward_batch", "backward", "grid", "plan_device", "plan_host", "foveate", "FoveateFn",
-                "tensor_desc"):
+                "tensor_desc", "profile_begin", "profile_end"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -28,6 +28,20 @@ class FovParams(ctypes.Structure):
                 ("sigma_map", ctypes.c_void_p)]
 
 
+class FovServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_batch_frames", ctypes.c_int32),
+                ("max_inflight_batches", ctypes.c_int32), ("max_requests", ctypes.c_int32),
+                ("in_dtype", ctypes.c_int32), ("out_dtype", ctypes.c_int32), ("max_fragments", ctypes.c_int32),
+                ("max_block", ctypes.c_int32), ("max_sigma", ctypes.c_double), ("use_graph", ctypes.c_int32),
+                ("test_fake_device_us", ctypes.c_int32), ("test_fail_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class FovTiming(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("batch_frames", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 # Every symbol declared in include/foveate.h, with (restype, argtypes).
 _TP = ctypes.POINTER(FovTensor)
 _PP = ctypes.POINTER(FovParams)
@@ -40,6 +54,14 @@ SIGNATURES = {
     "foveate_forward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
     "foveate_forward_batch": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
     "foveate_backward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
+    "foveate_profile_begin": (ctypes.c_int, [ctypes.c_int32]),
+    "foveate_profile_end": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _I32P]),
+    "foveate_now": (ctypes.c_double, []),
+    "foveate_server_create": (ctypes.c_int, [ctypes.POINTER(FovServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
+    "foveate_submit": (ctypes.c_int, [ctypes.c_void_p, _TP, _TP, _PP, ctypes.POINTER(ctypes.c_uint64)]),
+    "foveate_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, _I32P, ctypes.POINTER(FovTiming)]),
+    "foveate_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
+    "foveate_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "foveate_last_error": (ctypes.c_char_p, []),
     "foveate_version": (ctypes.c_char_p, []),
 }

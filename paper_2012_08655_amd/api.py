@@ -129,6 +129,19 @@ def backward(grad_out: torch.Tensor, params, grad_in: torch.Tensor | None = None
     return grad_in
 
 
+def profile_begin(capacity: int):
+    """Start recording main-kernel durations of this thread's forward calls."""
+    N.check(N.lib().foveate_profile_begin(int(capacity)))
+
+
+def profile_end(capacity: int) -> np.ndarray:
+    """Wait for and return the recorded main-kernel durations (ms)."""
+    buf = (ctypes.c_float * max(int(capacity), 1))()
+    cnt = ctypes.c_int32()
+    N.check(N.lib().foveate_profile_end(buf, int(capacity), ctypes.byref(cnt)))
+    return np.array(buf[:cnt.value], dtype=np.float64)
+
+
 def grid(h: int, w: int, params: Mapping) -> tuple[int, int]:
     """(nby, nbx) fragment rows/columns of an h x w frame."""
     p = N.make_params(params)

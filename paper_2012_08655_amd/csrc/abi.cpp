@@ -17,27 +17,24 @@
 #include "adjoint.h"
 #include "common.h"
 #include "forward.h"
+#include "host.h"
 
 namespace fov {
 
 namespace {
 thread_local std::string g_last_error;
-
-struct DeviceInfo {
-    bool ready = false;
-    size_t lds_limit = 0;  // dynamic LDS one workgroup may use
-    int cus = 0;
-};
 constexpr int kMaxDevices = 64;
 DeviceInfo g_dev[kMaxDevices];
 std::mutex g_dev_mu;
+}  // namespace
+
+const std::string& last_error() { return g_last_error; }
 
 int env_int(const char* name, int dflt) {
     const char* v = std::getenv(name);
     if (!v || !*v) return dflt;
     return std::atoi(v);
 }
-}  // namespace
 
 fov_status set_error(fov_status s, const std::string& msg) {
     g_last_error = msg;
@@ -73,24 +70,16 @@ fov_status device_info(const DeviceInfo** out) {
     return FOV_OK;
 }
 
-namespace {
-
 // Library-owned workspace, one per (device, stream): work queued on one stream
 // is ordered, so consecutive calls on that stream may reuse it.  It holds a
 // device buffer (plans, queues, frame tables) and a pinned host buffer for
 // uploading frame tables.  Both only grow; before a device buffer in use is
 // freed the stream is drained, and before the pinned buffer is rewritten the
 // previous upload from it is waited for.
-struct Workspace {
-    void* dev = nullptr;
-    size_t dev_bytes = 0;
-    void* host = nullptr;
-    size_t host_bytes = 0;
-    hipEvent_t upload_done = nullptr;
-    bool upload_pending = false;
-};
+namespace {
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+}  // namespace
 
 fov_status workspace(hipStream_t stream, size_t dev_bytes, size_t host_bytes, Workspace** out) {
     int dev = 0;
@@ -237,6 +226,27 @@ int frame_r_max(const FrameParams& f, int h) {
     return r;
 }
 
+namespace {
+// Per-thread kernel timing (foveate_profile_begin/end): event pairs recorded
+// around each main forward kernel while active.
+struct Profiler {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+};
+thread_local Profiler g_prof;
+
+void profile_release() {
+    for (auto& pr : g_prof.ev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    g_prof.ev.clear();
+    g_prof.used = 0;
+    g_prof.on = false;
+}
+}  // namespace
+
 // Dispatch of the main forward kernel: FOV_PERSISTENT=1 selects the
 // persistent grid; by default each fragment is its own workgroup (measured
 // faster on MI355X for single frames and batches alike).
@@ -253,7 +263,117 @@ int choose_strip_rows() {
     return forced > 0 && forced < mx ? forced : mx;
 }
 
-}  // namespace
+// Shared validation of forward/backward arguments.
+fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
+                          bool backward, bool* empty) {
+    fov_status s;
+    if ((s = check_view(in, backward ? "grad_out" : "in", false)) != FOV_OK) return s;
+    if ((s = check_view(out, backward ? "grad_in" : "out", true)) != FOV_OK) return s;
+    if (in->n != out->n || in->c != out->c || in->h != out->h || in->w != out->w)
+        return set_error(FOV_EINVAL, "input and output shapes differ");
+    if (backward) {
+        if (!((in->dtype == FOV_F32 && out->dtype == FOV_F32) || (in->dtype == FOV_F64 && out->dtype == FOV_F64)))
+            return set_error(FOV_EDTYPE, "backward supports f32->f32 and f64->f64");
+    } else {
+        bool ok = (in->dtype == FOV_U8 && (out->dtype == FOV_U8 || out->dtype == FOV_F32)) ||
+                  (in->dtype == FOV_F32 && out->dtype == FOV_F32) || (in->dtype == FOV_F64 && out->dtype == FOV_F64);
+        if (!ok) return set_error(FOV_EDTYPE, "unsupported dtype pair");
+    }
+    *empty = is_empty(*in);
+    if (*empty) return FOV_OK;
+    if ((s = check_alias(*in, *out)) != FOV_OK) return s;
+    if (!p) return set_error(FOV_EINVAL, "params is NULL");
+    if (np != in->n && np != 1) return set_error(FOV_EINVAL, "np must equal n or 1");
+    for (int i = 0; i < np; ++i)
+        if ((s = check_params(p[i], i)) != FOV_OK) return s;
+    return FOV_OK;
+}
+
+// One persistent forward launch over a list of frames (any shapes, one dtype
+// pair).  Up to kArgFrames descriptors travel in the kernel arguments; more
+// are uploaded as a device table from pinned memory.
+fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream) {
+    fov_status s;
+    const DeviceInfo* dev = nullptr;
+    if ((s = device_info(&dev)) != FOV_OK) return s;
+    const int nf = (int)frames.size();
+    if (nf == 0) return FOV_OK;
+    std::vector<int32_t> prefix(nf + 1);
+    int64_t total = 0;
+    int r_cap = 0, bmax = 1;
+    for (int i = 0; i < nf; ++i) {
+        prefix[i] = (int32_t)total;
+        total += (int64_t)frames[i].p.nbx * frames[i].nby;
+        r_cap = std::max(r_cap, frame_r_max(frames[i].p, frames[i].h));
+        bmax = std::max(bmax, frames[i].p.block);
+    }
+    if (total > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
+    prefix[nf] = (int32_t)total;
+    const int sr = choose_strip_rows();
+    const size_t lds = forward_lds_bytes(in_dtype, r_cap, bmax, sr);
+    if (lds + 64 > dev->lds_limit)
+        return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
+                                         " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
+    const int wsize = in_dtype == FOV_F64 ? 8 : 4;
+    FwdLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.nframes = nf;
+    a.nfrag = (int32_t)total;
+    a.r_cap = r_cap;
+    a.strip_rows = sr;
+    a.wstride = round_up(2 * r_cap + 1, 16);
+    a.nslots = queue_slots(a.nfrag, r_cap);
+    const size_t pbytes = (plan_bytes(a.nfrag, a.nslots, a.wstride, wsize) + 255) / 256 * 256;
+    const bool upload = nf > kArgFrames;
+    const size_t tbytes = ((size_t)nf * sizeof(FrameDesc) + (size_t)(nf + 1) * 4 + 255) / 256 * 256;
+    Workspace* ws = nullptr;
+    if ((s = workspace(stream, pbytes + tbytes, upload ? tbytes : 0, &ws)) != FOV_OK) return s;
+    const PlanBuffers plan = carve_plan(ws->dev, a.nfrag, a.nslots);
+    char* dtab = static_cast<char*>(ws->dev) + pbytes;
+    a.table = reinterpret_cast<FrameDesc*>(dtab);
+    a.prefix = reinterpret_cast<int32_t*>(dtab + (size_t)nf * sizeof(FrameDesc));
+    if (upload) {
+        if (ws->upload_pending) {
+            hipError_t e = hipEventSynchronize(ws->upload_done);
+            if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(upload)");
+            ws->upload_pending = false;
+        }
+        char* hst = static_cast<char*>(ws->host);
+        std::memcpy(hst, frames.data(), (size_t)nf * sizeof(FrameDesc));
+        std::memcpy(hst + (size_t)nf * sizeof(FrameDesc), prefix.data(), (size_t)(nf + 1) * 4);
+        hipError_t e = hipMemcpyAsync(dtab, hst, tbytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(frame table)");
+        e = hipEventRecord(ws->upload_done, stream);
+        if (e != hipSuccess) return hip_error(e, "hipEventRecord(upload)");
+        ws->upload_pending = true;
+    } else {
+        a.from_args = 1;
+        for (int i = 0; i < nf; ++i) a.fr[i] = frames[i];
+        for (int i = 0; i <= nf; ++i) a.kprefix[i] = prefix[i];
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_prof.on && g_prof.used < g_prof.ev.size()) {
+        e0 = g_prof.ev[g_prof.used].first;
+        e1 = g_prof.ev[g_prof.used].second;
+        ++g_prof.used;
+    }
+    return launch_forward(a, in_dtype, out_dtype, lds, plan, stream, dev->lds_limit, dev->cus, dispatch_persistent(),
+                          e0, e1);
+}
+
+FrameDesc make_frame_desc(const fov_tensor& in, const fov_tensor& out, int n, const fov_params& p) {
+    const size_t ei = dtype_size(in.dtype), eo = dtype_size(out.dtype);
+    FrameDesc d;
+    d.in = static_cast<const char*>(in.data) + (size_t)n * in.sn * ei;
+    d.out = static_cast<char*>(out.data) + (size_t)n * out.sn * eo;
+    d.isc = in.sc; d.ish = in.sh; d.isw = in.sw;
+    d.osc = out.sc; d.osh = out.sh; d.osw = out.sw;
+    d.c = in.c; d.h = in.h; d.w = in.w;
+    d.p = to_frame(p, in.h, in.w);
+    d.nby = grid_extent(in.h, p.origin_y, p.block);
+    return d;
+}
+
 }  // namespace fov
 
 using namespace fov;
@@ -263,6 +383,45 @@ extern "C" {
 const char* foveate_last_error(void) { return g_last_error.c_str(); }
 
 const char* foveate_version(void) { return "libfoveate 0.1 (gfx950)"; }
+
+fov_status foveate_profile_begin(int32_t capacity) {
+    if (capacity < 1 || capacity > (1 << 20)) return set_error(FOV_EINVAL, "capacity must be in 1..2^20");
+    profile_release();
+    g_prof.ev.reserve(capacity);
+    for (int i = 0; i < capacity; ++i) {
+        hipEvent_t a = nullptr, b = nullptr;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            if (a) (void)hipEventDestroy(a);
+            profile_release();
+            return hip_error(e, "hipEventCreate(profile)");
+        }
+        g_prof.ev.emplace_back(a, b);
+    }
+    g_prof.on = true;
+    return FOV_OK;
+}
+
+fov_status foveate_profile_end(float* ms, int32_t capacity, int32_t* count) {
+    if (!count) return set_error(FOV_EINVAL, "count is NULL");
+    *count = 0;
+    if (!g_prof.on) return set_error(FOV_EINVAL, "profiling was not started");
+    const int n = (int)std::min(g_prof.used, (size_t)std::max(capacity, 0));
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = hipEventSynchronize(g_prof.ev[i].second);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, g_prof.ev[i].first, g_prof.ev[i].second);
+        if (e != hipSuccess) {
+            profile_release();
+            return hip_error(e, "hipEventElapsedTime(profile)");
+        }
+        if (ms) ms[i] = t;
+    }
+    *count = n;
+    profile_release();
+    return FOV_OK;
+}
 
 fov_status foveate_grid(int32_t h, int32_t w, const fov_params* p, int32_t* nbx, int32_t* nby) {
     if (!p || !nbx || !nby) return set_error(FOV_EINVAL, "NULL argument");
@@ -298,109 +457,6 @@ fov_status foveate_plan(int32_t h, int32_t w, const fov_params* p, double* sigma
     return launch_plan(to_frame(*p, h, w), nbx * nby, sigma_out, r_out, (hipStream_t)stream);
 }
 
-// Shared validation of forward/backward arguments; fills frames[] and r_max.
-static fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
-                          bool backward, bool* empty) {
-    fov_status s;
-    if ((s = check_view(in, backward ? "grad_out" : "in", false)) != FOV_OK) return s;
-    if ((s = check_view(out, backward ? "grad_in" : "out", true)) != FOV_OK) return s;
-    if (in->n != out->n || in->c != out->c || in->h != out->h || in->w != out->w)
-        return set_error(FOV_EINVAL, "input and output shapes differ");
-    if (backward) {
-        if (!((in->dtype == FOV_F32 && out->dtype == FOV_F32) || (in->dtype == FOV_F64 && out->dtype == FOV_F64)))
-            return set_error(FOV_EDTYPE, "backward supports f32->f32 and f64->f64");
-    } else {
-        bool ok = (in->dtype == FOV_U8 && (out->dtype == FOV_U8 || out->dtype == FOV_F32)) ||
-                  (in->dtype == FOV_F32 && out->dtype == FOV_F32) || (in->dtype == FOV_F64 && out->dtype == FOV_F64);
-        if (!ok) return set_error(FOV_EDTYPE, "unsupported dtype pair");
-    }
-    *empty = is_empty(*in);
-    if (*empty) return FOV_OK;
-    if ((s = check_alias(*in, *out)) != FOV_OK) return s;
-    if (!p) return set_error(FOV_EINVAL, "params is NULL");
-    if (np != in->n && np != 1) return set_error(FOV_EINVAL, "np must equal n or 1");
-    for (int i = 0; i < np; ++i)
-        if ((s = check_params(p[i], i)) != FOV_OK) return s;
-    return FOV_OK;
-}
-
-// One persistent forward launch over a list of frames (any shapes, one dtype
-// pair).  Up to kArgFrames descriptors travel in the kernel arguments; more
-// are uploaded as a device table from pinned memory.
-static fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream) {
-    fov_status s;
-    const DeviceInfo* dev = nullptr;
-    if ((s = device_info(&dev)) != FOV_OK) return s;
-    const int nf = (int)frames.size();
-    if (nf == 0) return FOV_OK;
-    std::vector<int32_t> prefix(nf + 1);
-    int64_t total = 0;
-    int r_cap = 0, bmax = 1;
-    for (int i = 0; i < nf; ++i) {
-        prefix[i] = (int32_t)total;
-        total += (int64_t)frames[i].p.nbx * frames[i].nby;
-        r_cap = std::max(r_cap, frame_r_max(frames[i].p, frames[i].h));
-        bmax = std::max(bmax, frames[i].p.block);
-    }
-    if (total > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
-    prefix[nf] = (int32_t)total;
-    const int sr = choose_strip_rows();
-    const size_t lds = forward_lds_bytes(in_dtype, r_cap, bmax, sr);
-    if (lds + 64 > dev->lds_limit)
-        return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
-                                         " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
-    const int wsize = in_dtype == FOV_F64 ? 8 : 4;
-    FwdLaunch a;
-    std::memset(&a, 0, sizeof(a));
-    a.nframes = nf;
-    a.nfrag = (int32_t)total;
-    a.r_cap = r_cap;
-    a.strip_rows = sr;
-    a.wstride = round_up(2 * r_cap + 1, 16);
-    const size_t pbytes = (plan_bytes(a.nfrag, a.wstride, wsize) + 255) / 256 * 256;
-    const bool upload = nf > kArgFrames;
-    const size_t tbytes = ((size_t)nf * sizeof(FrameDesc) + (size_t)(nf + 1) * 4 + 255) / 256 * 256;
-    Workspace* ws = nullptr;
-    if ((s = workspace(stream, pbytes + tbytes, upload ? tbytes : 0, &ws)) != FOV_OK) return s;
-    const PlanBuffers plan = carve_plan(ws->dev, a.nfrag, a.wstride, wsize);
-    char* dtab = static_cast<char*>(ws->dev) + pbytes;
-    a.table = reinterpret_cast<FrameDesc*>(dtab);
-    a.prefix = reinterpret_cast<int32_t*>(dtab + (size_t)nf * sizeof(FrameDesc));
-    if (upload) {
-        if (ws->upload_pending) {
-            hipError_t e = hipEventSynchronize(ws->upload_done);
-            if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(upload)");
-            ws->upload_pending = false;
-        }
-        char* hst = static_cast<char*>(ws->host);
-        std::memcpy(hst, frames.data(), (size_t)nf * sizeof(FrameDesc));
-        std::memcpy(hst + (size_t)nf * sizeof(FrameDesc), prefix.data(), (size_t)(nf + 1) * 4);
-        hipError_t e = hipMemcpyAsync(dtab, hst, tbytes, hipMemcpyHostToDevice, stream);
-        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(frame table)");
-        e = hipEventRecord(ws->upload_done, stream);
-        if (e != hipSuccess) return hip_error(e, "hipEventRecord(upload)");
-        ws->upload_pending = true;
-    } else {
-        a.from_args = 1;
-        for (int i = 0; i < nf; ++i) a.fr[i] = frames[i];
-        for (int i = 0; i <= nf; ++i) a.kprefix[i] = prefix[i];
-    }
-    return launch_forward(a, in_dtype, out_dtype, lds, plan, stream, dev->lds_limit, dev->cus, dispatch_persistent());
-}
-
-static FrameDesc frame_desc(const fov_tensor& in, const fov_tensor& out, int n, const fov_params& p) {
-    const size_t ei = dtype_size(in.dtype), eo = dtype_size(out.dtype);
-    FrameDesc d;
-    d.in = static_cast<const char*>(in.data) + (size_t)n * in.sn * ei;
-    d.out = static_cast<char*>(out.data) + (size_t)n * out.sn * eo;
-    d.isc = in.sc; d.ish = in.sh; d.isw = in.sw;
-    d.osc = out.sc; d.osh = out.sh; d.osw = out.sw;
-    d.c = in.c; d.h = in.h; d.w = in.w;
-    d.p = to_frame(p, in.h, in.w);
-    d.nby = grid_extent(in.h, p.origin_y, p.block);
-    return d;
-}
-
 fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
                            void* stream) {
     bool empty = false;
@@ -408,7 +464,7 @@ fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fo
     if (s != FOV_OK || empty) return s;
     std::vector<FrameDesc> frames;
     frames.reserve(in->n);
-    for (int i = 0; i < in->n; ++i) frames.push_back(frame_desc(*in, *out, i, p[np == 1 ? 0 : i]));
+    for (int i = 0; i < in->n; ++i) frames.push_back(make_frame_desc(*in, *out, i, p[np == 1 ? 0 : i]));
     return run_forward(frames, in->dtype, out->dtype, (hipStream_t)stream);
 }
 
@@ -423,13 +479,13 @@ fov_status foveate_forward_batch(const fov_tensor* ins, const fov_tensor* outs, 
     for (int i = 0; i < nframes; ++i) {
         bool empty = false;
         fov_status s = prepare(&ins[i], &outs[i], &ps[i], 1, false, &empty);
-        if (s != FOV_OK) return set_error(s, "frame " + std::to_string(i) + ": " + g_last_error);
+        if (s != FOV_OK) return set_error(s, "frame " + std::to_string(i) + ": " + last_error());
         if (empty) continue;
         if (ins[i].n != 1) return set_error(FOV_EINVAL, "frame " + std::to_string(i) + ": each view must hold one frame");
         if (dt_in < 0) { dt_in = ins[i].dtype; dt_out = outs[i].dtype; }
         if (ins[i].dtype != dt_in || outs[i].dtype != dt_out)
             return set_error(FOV_EDTYPE, "all frames of a batch must share one dtype pair");
-        frames.push_back(frame_desc(ins[i], outs[i], 0, ps[i]));
+        frames.push_back(make_frame_desc(ins[i], outs[i], 0, ps[i]));
     }
     // outputs of different frames must not overlap inputs of others either
     for (int i = 0; i < nframes; ++i)

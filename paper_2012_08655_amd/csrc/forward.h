@@ -23,6 +23,8 @@ constexpr int kArgFrames = 16;
 // [prefix[f], prefix[f+1]).
 struct FwdLaunch {
     int32_t nframes, nfrag;
+    int32_t nslots;      // queue slots (fragments plus empty padding slots)
+    int32_t pad0_;
     int32_t r_cap;       // largest radius the LDS allocation was sized for
     int32_t strip_rows;  // padded-tile rows staged in LDS at once
     int32_t wstride;     // weights per fragment in the plan workspace (multiple of 16)
@@ -30,26 +32,39 @@ struct FwdLaunch {
                          // copies them to table/prefix; 0: table/prefix were uploaded
     FrameDesc* table;    // device table of nframes entries (read by the main kernel)
     int32_t* prefix;     // device array of nframes+1 entries
+    const int32_t* hdr;  // optional device header {nframes, nfrag, nslots}: when set, the kernels
+                         // read the counts there and the fields above are capacities (a launch
+                         // sequence that can be captured once and replayed for many batches)
     int32_t kprefix[kArgFrames + 1];
     FrameDesc fr[kArgFrames];
 };
 static_assert(sizeof(FwdLaunch) <= 4000, "kernel arguments must fit the kernarg segment");
 
+// Device header of a replayable batch (see FwdLaunch::hdr).
+struct BatchHeader {
+    int32_t nframes, nfrag, nslots, pad;
+};
+
 // Plan workspace of one launch.
 struct PlanBuffers {
     int32_t* radius;   // [nfrag] radius of each fragment
-    int32_t* order;    // [nfrag] fragment ids by decreasing radius (queue order)
+    int32_t* okey;     // [nfrag] (ring, angle bin) cell of each fragment for the queue order
+    int32_t* order;    // [nslots] queue: fragment ids (-1 = empty slot), see the order kernel
     void* weights;     // [nfrag][wstride] normalised taps, float (u8/f32) or double (f64)
 };
 
-size_t plan_bytes(int nfrag, int wstride, int wsize);
-PlanBuffers carve_plan(void* ws, int nfrag, int wstride, int wsize);
+int queue_slots(int nfrag, int r_cap);
+size_t plan_bytes(int nfrag, int nslots, int wstride, int wsize);
+PlanBuffers carve_plan(void* ws, int nfrag, int nslots);
 
 // Plan + order + main kernel for one launch.  persist selects the dispatch of
 // the main kernel: a persistent grid striding over the queue, or one
 // workgroup per fragment handed out by the hardware dispatcher.
+// ev_start/ev_stop, when not null, are recorded on `stream` right before and
+// right after the main kernel.
 fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,
-                          hipStream_t stream, size_t lds_limit, int cus, bool persist);
+                          hipStream_t stream, size_t lds_limit, int cus, bool persist,
+                          hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Device plan for foveate_plan(): sigma and radius of every fragment.
 fov_status launch_plan(const FrameParams& fp, int nblk, double* sigma_out, int32_t* r_out, hipStream_t stream);

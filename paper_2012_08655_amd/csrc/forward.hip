@@ -505,45 +505,76 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
                                                            const FrameDesc* __restrict__ table,
                                                            const int32_t* __restrict__ prefix) {
     extern __shared__ __align__(16) unsigned char smem[];
-    for (int q = blockIdx.x; q < a.nfrag; q += gridDim.x) {
+    const int nslots = a.hdr ? a.hdr[2] : a.nslots;
+    const int nframes = a.hdr ? a.hdr[0] : a.nframes;
+    for (int q = blockIdx.x; q < nslots; q += gridDim.x) {
         const int gid = order[q];
+        if (gid < 0) {  // empty slot
+            if (!PERSIST) break;
+            continue;
+        }
         const int r = radius[gid];
-        const Frag F = describe(table, prefix, a.nframes, gid);
+        const Frag F = describe(table, prefix, nframes, gid);
         process_fragment<TIn, TOut, TS, TC>(a, gid, r, F, wts, smem);
         if (!PERSIST) break;
         __syncthreads();  // this fragment's LDS reads are done before the next one is staged
     }
 }
 
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderMaxRings = 1024;
+constexpr int kOrderCells = 12288;
+constexpr int kXcds = 8;
+
+// Rings (distinct radii) and angle bins of the order histogram.
+int order_rings(int r_cap) { return std::min(r_cap + 1, kOrderMaxRings); }
+int order_angle_bins(int nrings) { return std::max(1, std::min(64, kOrderCells / nrings)); }
+
+__device__ __forceinline__ int angle_bin(const Frag& F, int nang) {
+    const FrameParams& fp = F.fd->p;
+    const float half = 0.5f * (float)(fp.block - 1);
+    const float cx = (float)(fp.origin_x + F.bx * fp.block) + half;
+    const float cy = (float)(fp.origin_y + F.by * fp.block) + half;
+    const float th = atan2f(cy - (float)fp.fix_y, cx - (float)fp.fix_x);  // (-pi, pi]
+    int b = (int)((th + 3.14159265f) * (float)nang * 0.159154943f);
+    return b < 0 ? 0 : (b >= nang ? nang - 1 : b);
+}
+
 // ---- plan kernels --------------------------------------------------------------------------------
 // Fragment plan: radius and normalised taps, one wavefront per fragment.
 template <typename TC>
 __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a, int32_t* __restrict__ radius,
+                                                              int32_t* __restrict__ okey, int nrings, int nang,
                                                               TC* __restrict__ wts) {
-    const int gid = blockIdx.x;
     const int lane = threadIdx.x;
+    const int nframes = a.hdr ? a.hdr[0] : a.nframes;
+    const int nfrag = a.hdr ? a.hdr[1] : a.nfrag;
+    for (int gid = blockIdx.x; gid < nfrag; gid += gridDim.x) {
     Frag F;
     if (a.from_args) {
         int f = 0;
-        while (f + 1 < a.nframes && gid >= a.kprefix[f + 1]) ++f;
+        while (f + 1 < nframes && gid >= a.kprefix[f + 1]) ++f;
         F = describe_at(&a.fr[f], a.kprefix[f], gid);
         if (gid == 0) {
             // publish the frame table for the main kernel
             constexpr int kWords = sizeof(FrameDesc) / 4;
             const int32_t* src = reinterpret_cast<const int32_t*>(a.fr);
             int32_t* dst = reinterpret_cast<int32_t*>(a.table);
-            for (int i = lane; i < a.nframes * kWords; i += 64) dst[i] = src[i];
-            for (int i = lane; i <= a.nframes; i += 64) a.prefix[i] = a.kprefix[i];
+            for (int i = lane; i < nframes * kWords; i += 64) dst[i] = src[i];
+            for (int i = lane; i <= nframes; i += 64) a.prefix[i] = a.kprefix[i];
         }
     } else {
-        F = describe(a.table, a.prefix, a.nframes, gid);
+        F = describe(a.table, a.prefix, nframes, gid);
     }
     const FrameParams& fp = F.fd->p;
     const double sigma = fp.sigma_map ? clip_map_sigma((double)fp.sigma_map[F.lb], fp.cap)
                                       : fragment_sigma_ramp(fp, F.bx, F.by);
     int r = radius_of(sigma);
     if (r > a.r_cap) r = a.r_cap;  // the host sized everything for r_cap; plans agree bit for bit
-    if (lane == 0) radius[gid] = r;
+    if (lane == 0) {
+        radius[gid] = r;
+        okey[gid] = (nrings - 1 - min(r, nrings - 1)) * nang + angle_bin(F, nang);  // (ring, angle bin) cell
+    }
     const int N = 2 * r + 1;
     const double inv = r > 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
     constexpr int kHeld = 4;  // taps per lane kept in registers
@@ -575,43 +606,91 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
         }
         wr[j] = (TC)v;
     }
+    }
 }
 
-// Queue order: fragments by decreasing radius (their cost grows with r), so
-// the costliest start first and the launch does not end on a long tail.  One
-// workgroup: LDS histogram of radii, exclusive scan from the top, scatter; the
-// order among equal radii is arbitrary and results do not depend on it.
-constexpr int kOrderThreads = 1024;
-constexpr int kOrderBins = 1024;
+// Queue order.  Fragments go by decreasing radius (their cost grows with r), so
+// the costliest start first and the launch does not end on a long tail.
+// Workgroup q runs on XCD q mod 8 (the dispatcher deals workgroups to the
+// eight XCDs in turn), and each XCD has its own L2: neighbouring fragments
+// share halo rows, so within every radius ring the fragments are sorted by
+// angle around their frame's fixation and cut into eight contiguous arcs, arc
+// a going to slots congruent to a mod 8.  Each XCD thus works through one
+// angular sector ring by ring, with an equal share of every ring.  Rings are
+// padded to a multiple of 8 slots with empty slots (-1).
+// One workgroup: LDS histogram over (ring, angle bin), scans, scatter; the
+// order inside one (ring, angle bin) cell is arbitrary and results do not
+// depend on it.
 
-__global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t* __restrict__ radius, int n,
-                                                                  int nbins, int32_t* __restrict__ order) {
-    __shared__ int bins[kOrderBins];
-    for (int i = threadIdx.x; i < nbins; i += kOrderThreads) bins[i] = 0;
+__global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t* __restrict__ okey, int n_arg,
+                                                                  int nrings, int nang, int nslots_arg,
+                                                                  const int32_t* __restrict__ hdr,
+                                                                  int32_t* __restrict__ order) {
+    const int n = hdr ? hdr[1] : n_arg;
+    const int nslots = hdr ? hdr[2] : nslots_arg;
+    __shared__ int cells[kOrderCells];        // [ring][angle bin], ring 0 = largest radius
+    __shared__ int ring_n[kOrderMaxRings];    // fragments per ring
+    __shared__ int ring_base[kOrderMaxRings]; // first slot of each ring (multiple of 8)
+    __shared__ int total_slots;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ncell = nrings * nang;
+    for (int i = tid; i < ncell; i += kOrderThreads) cells[i] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kOrderThreads) atomicAdd(&bins[min(radius[i], nbins - 1)], 1);
+    for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&cells[okey[i]], 1);
     __syncthreads();
-    if (threadIdx.x < 64) {
-        // exclusive scan from the largest radius down, 64 bins per step
-        const int lane = threadIdx.x;
+    // exclusive scan of the angle bins inside each ring (one wave per ring)
+    for (int ring = wave; ring < nrings; ring += kOrderThreads / 64) {
         int carry = 0;
-        for (int b0 = 0; b0 < nbins; b0 += 64) {
-            const int b = nbins - 1 - (b0 + lane);
-            const int v = b >= 0 ? bins[b] : 0;
+        for (int b0 = 0; b0 < nang; b0 += 64) {
+            const int b = b0 + lane;
+            const int v = b < nang ? cells[ring * nang + b] : 0;
             int incl = v;
             for (int off = 1; off < 64; off <<= 1) {
                 const int t = __shfl_up(incl, off, 64);
                 if (lane >= off) incl += t;
             }
-            if (b >= 0) bins[b] = carry + incl - v;
+            if (b < nang) cells[ring * nang + b] = carry + incl - v;
             carry += __shfl(incl, 63, 64);
         }
+        if (lane == 0) ring_n[ring] = carry;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kOrderThreads) {
-        const int pos = atomicAdd(&bins[min(radius[i], nbins - 1)], 1);
-        order[pos] = i;
+    if (wave == 0) {
+        // ring bases: each ring takes 8 * ceil(n_ring / 8) slots
+        int carry = 0;
+        for (int r0 = 0; r0 < nrings; r0 += 64) {
+            const int ring = r0 + lane;
+            const int v = ring < nrings ? round_up(ring_n[ring], kXcds) : 0;
+            int incl = v;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += t;
+            }
+            if (ring < nrings) ring_base[ring] = carry + incl - v;
+            carry += __shfl(incl, 63, 64);
+        }
+        if (lane == 0) total_slots = carry;
     }
+    __syncthreads();
+    for (int i = tid; i < n; i += kOrderThreads) {
+        const int key = okey[i];
+        const int ring = key / nang;
+        const int j = atomicAdd(&cells[key], 1);  // rank in the ring
+        const int m = ring_n[ring];
+        const int arc = (j * kXcds) / m;                  // arc a holds ranks [ceil(a m/8), ceil((a+1) m/8))
+        const int k = j - (arc * m + kXcds - 1) / kXcds;  // rank inside the arc
+        order[ring_base[ring] + kXcds * k + arc] = i;
+    }
+    // empty slots: arc a of a ring of m holds ceil((a+1)m/8) - ceil(a m/8) <= ceil(m/8) fragments
+    for (int ring = wave; ring < nrings; ring += kOrderThreads / 64) {
+        const int m = ring_n[ring], per = (m + kXcds - 1) / kXcds;
+        for (int t = lane; t < per * kXcds; t += 64) {
+            const int arc = t % kXcds, k = t / kXcds;
+            const int sz = ((arc + 1) * m + kXcds - 1) / kXcds - (arc * m + kXcds - 1) / kXcds;
+            if (k >= sz) order[ring_base[ring] + kXcds * k + arc] = -1;
+        }
+    }
+    for (int q = total_slots + tid; q < nslots; q += kOrderThreads) order[q] = -1;
 }
 
 // Device plan for foveate_plan(): sigma and radius only.
@@ -639,7 +718,7 @@ int FwdSlot<TIn, TOut, TS, TC, PERSIST>::occ_blocks = 0;
 
 template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
 fov_status launch_main(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, hipStream_t stream,
-                       size_t lds_limit, int cus) {
+                       size_t lds_limit, int cus, hipEvent_t ev_start, hipEvent_t ev_stop) {
     using Slot = FwdSlot<TIn, TOut, TS, TC, PERSIST>;
     auto kern = fov_fwd_kernel<TIn, TOut, TS, TC, PERSIST>;
     hipError_t e;
@@ -652,7 +731,7 @@ fov_status launch_main(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, 
         if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(forward)");
         Slot::configured = true;
     }
-    int grid = a.nfrag;
+    int grid = a.nslots;
     if (PERSIST) {
         if (Slot::occ_lds != lds) {
             int nb = 0;
@@ -661,29 +740,34 @@ fov_status launch_main(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, 
             Slot::occ_blocks = std::max(nb, 1);
             Slot::occ_lds = lds;
         }
-        grid = std::max(1, std::min(a.nfrag, Slot::occ_blocks * cus));
+        grid = std::max(1, std::min(a.nslots, Slot::occ_blocks * cus));
     }
+    if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return hip_error(e, "hipEventRecord");
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, stream, a, (const int32_t*)plan.radius,
                        (const TC*)plan.weights, (const int32_t*)plan.order, (const FrameDesc*)a.table,
                        (const int32_t*)a.prefix);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "forward kernel launch");
+    if (ev_stop && (e = hipEventRecord(ev_stop, stream)) != hipSuccess) return hip_error(e, "hipEventRecord");
     return FOV_OK;
 }
 
 template <typename TIn, typename TOut, typename TS, typename TC>
 fov_status launch_typed(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, hipStream_t stream,
-                        size_t lds_limit, int cus, bool persist) {
+                        size_t lds_limit, int cus, bool persist, hipEvent_t ev_start, hipEvent_t ev_stop) {
     TC* wts = static_cast<TC*>(plan.weights);
-    hipLaunchKernelGGL(fov_plan_weights_kernel<TC>, dim3(a.nfrag), dim3(64), 0, stream, a, plan.radius, wts);
+    const int nrings = order_rings(a.r_cap), nang = order_angle_bins(nrings);
+    const int plan_grid = a.hdr ? std::min(a.nfrag, 8192) : a.nfrag;
+    hipLaunchKernelGGL(fov_plan_weights_kernel<TC>, dim3(plan_grid), dim3(64), 0, stream, a, plan.radius, plan.okey,
+                       nrings, nang, wts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "plan kernel launch");
-    hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.radius,
-                       a.nfrag, std::min(a.r_cap + 1, kOrderBins), plan.order);
+    hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.okey, a.nfrag,
+                       nrings, nang, a.nslots, a.hdr, plan.order);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "order kernel launch");
-    if (persist) return launch_main<TIn, TOut, TS, TC, true>(a, lds, plan, stream, lds_limit, cus);
-    return launch_main<TIn, TOut, TS, TC, false>(a, lds, plan, stream, lds_limit, cus);
+    if (persist || a.hdr) return launch_main<TIn, TOut, TS, TC, true>(a, lds, plan, stream, lds_limit, cus, ev_start, ev_stop);
+    return launch_main<TIn, TOut, TS, TC, false>(a, lds, plan, stream, lds_limit, cus, ev_start, ev_stop);
 }
 
 int stage_size(int in_dtype) { return in_dtype == FOV_U8 ? 2 : (in_dtype == FOV_F32 ? 4 : 8); }
@@ -691,18 +775,20 @@ int compute_size(int in_dtype) { return in_dtype == FOV_F64 ? 8 : 4; }
 
 }  // namespace
 
-size_t plan_bytes(int nfrag, int wstride, int wsize) {
-    return 2 * align16((size_t)nfrag * 4) + 256 + (size_t)nfrag * wstride * wsize;
+int queue_slots(int nfrag, int r_cap) { return nfrag + kXcds * order_rings(r_cap); }
+
+size_t plan_bytes(int nfrag, int nslots, int wstride, int wsize) {
+    return 2 * align16((size_t)nfrag * 4) + align16((size_t)nslots * 4) + 256 + (size_t)nfrag * wstride * wsize;
 }
 
-PlanBuffers carve_plan(void* ws, int nfrag, int wstride, int wsize) {
-    (void)wstride;
-    (void)wsize;
+PlanBuffers carve_plan(void* ws, int nfrag, int nslots) {
     PlanBuffers p;
     char* base = static_cast<char*>(ws);
+    const size_t f4 = align16((size_t)nfrag * 4);
     p.radius = reinterpret_cast<int32_t*>(base);
-    p.order = reinterpret_cast<int32_t*>(base + align16((size_t)nfrag * 4));
-    p.weights = base + 2 * align16((size_t)nfrag * 4) + 256;
+    p.okey = reinterpret_cast<int32_t*>(base + f4);
+    p.order = reinterpret_cast<int32_t*>(base + 2 * f4);
+    p.weights = base + 2 * f4 + align16((size_t)nslots * 4) + 256;
     return p;
 }
 
@@ -717,16 +803,17 @@ size_t forward_lds_bytes(int in_dtype, int r_cap, int B, int strip_rows) {
 }
 
 fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,
-                          hipStream_t stream, size_t lds_limit, int cus, bool persist) {
+                          hipStream_t stream, size_t lds_limit, int cus, bool persist, hipEvent_t ev_start,
+                          hipEvent_t ev_stop) {
     if (a.nfrag <= 0) return FOV_OK;
     if (in_dtype == FOV_U8 && out_dtype == FOV_U8)
-        return launch_typed<uint8_t, uint8_t, _Float16, float>(a, lds, plan, stream, lds_limit, cus, persist);
+        return launch_typed<uint8_t, uint8_t, _Float16, float>(a, lds, plan, stream, lds_limit, cus, persist, ev_start, ev_stop);
     if (in_dtype == FOV_U8 && out_dtype == FOV_F32)
-        return launch_typed<uint8_t, float, _Float16, float>(a, lds, plan, stream, lds_limit, cus, persist);
+        return launch_typed<uint8_t, float, _Float16, float>(a, lds, plan, stream, lds_limit, cus, persist, ev_start, ev_stop);
     if (in_dtype == FOV_F32 && out_dtype == FOV_F32)
-        return launch_typed<float, float, float, float>(a, lds, plan, stream, lds_limit, cus, persist);
+        return launch_typed<float, float, float, float>(a, lds, plan, stream, lds_limit, cus, persist, ev_start, ev_stop);
     if (in_dtype == FOV_F64 && out_dtype == FOV_F64)
-        return launch_typed<double, double, double, double>(a, lds, plan, stream, lds_limit, cus, persist);
+        return launch_typed<double, double, double, double>(a, lds, plan, stream, lds_limit, cus, persist, ev_start, ev_stop);
     return set_error(FOV_EDTYPE, "unsupported dtype pair");
 }
 

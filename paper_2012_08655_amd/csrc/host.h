@@ -1,0 +1,54 @@
+// Host-side helpers shared by the C ABI entry points and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "forward.h"
+
+namespace fov {
+
+struct DeviceInfo {
+    bool ready = false;
+    size_t lds_limit = 0;  // dynamic LDS one workgroup may use
+    int cus = 0;
+};
+fov_status device_info(const DeviceInfo** out);
+
+// Per-(device, stream) workspace: device buffer for plans and frame tables,
+// pinned host buffer for table uploads (see abi.cpp).
+struct Workspace {
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    void* host = nullptr;
+    size_t host_bytes = 0;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+};
+fov_status workspace(hipStream_t stream, size_t dev_bytes, size_t host_bytes, Workspace** out);
+
+const std::string& last_error();
+int env_int(const char* name, int dflt);
+
+size_t dtype_size(int dt);
+bool is_empty(const fov_tensor& t);
+fov_status check_view(const fov_tensor* t, const char* name, bool is_output);
+fov_status check_alias(const fov_tensor& a, const fov_tensor& b);
+fov_status check_params(const fov_params& p, int idx);
+FrameParams to_frame(const fov_params& p, int h, int w);
+int frame_r_max(const FrameParams& f, int h);
+int choose_strip_rows();
+bool dispatch_persistent();
+
+// Validation of a forward (or backward) call's views and parameters.
+fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np, bool backward,
+                   bool* empty);
+// Descriptor of frame n of a validated (in, out) pair.
+FrameDesc make_frame_desc(const fov_tensor& in, const fov_tensor& out, int n, const fov_params& p);
+// Plan, order and main kernels for a list of frames on `stream`.
+fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream);
+
+}  // namespace fov

@@ -1,0 +1,65 @@
+"""GPU tests of the serving loop: every served frame equals (bitwise) the
+same frame foveated alone with foveate_forward, whether it ran alone or in a
+batch with other frames, with and without hipGraph replay."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2012_08655_amd.server import Server
+
+pytestmark = pytest.mark.gpu
+
+
+def frames_and_params(n, seed, shapes=((48, 64), (120, 90), (200, 333), (31, 17))):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        h, w = shapes[int(rng.integers(len(shapes)))]
+        fr = synth.grating_frame(h, w, 3, seed=seed * 1000 + i)
+        p = synth.params_dict(rng.uniform(0, w - 1), rng.uniform(0, h - 1), rng.uniform(0, 40),
+                              rng.uniform(0.01, 0.1), rng.uniform(1, 16))
+        out.append((fr, p))
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_served_equals_plain(fov, dev, use_graph):
+    items = frames_and_params(40, seed=1 + int(use_graph))
+    ins = [torch.from_numpy(f).to(dev) for f, _ in items]
+    outs = [torch.empty_like(t) for t in ins]
+    plain = [fov.forward(t, p, layout="HWC") for t, (_, p) in zip(ins, items)]
+    torch.cuda.synchronize()
+    with Server(hbm_budget_bytes=256 << 20, max_batch_frames=16, max_inflight_batches=2, max_fragments=20000,
+                max_sigma=16.0, use_graph=use_graph) as s:
+        tickets = []
+        for k, (t, o, (_, p)) in enumerate(zip(ins, outs, items)):
+            tickets.append(s.submit(t, o, p))
+            if k % 7 == 0:
+                time.sleep(0.002)  # let batches start while others arrive
+        s.drain()
+        sizes = []
+        for tk in tickets:
+            done, tm = s.poll(tk)
+            assert done and tm.status == 0
+            assert tm.t_submit <= tm.t_admit <= tm.t_launch <= tm.t_done
+            sizes.append(tm.batch_frames)
+    for i in range(len(items)):
+        assert torch.equal(outs[i], plain[i]), i
+    assert max(sizes) > 1  # some frames ran batched
+
+
+def test_server_budget_smaller_than_batch(fov, dev):
+    # a budget of ~3 frames forces several small batches; results unchanged
+    items = frames_and_params(12, seed=9, shapes=((64, 64),))
+    ins = [torch.from_numpy(f).to(dev) for f, _ in items]
+    outs = [torch.empty_like(t) for t in ins]
+    budget = 3 * 2 * 64 * 64 * 3
+    with Server(hbm_budget_bytes=budget, max_batch_frames=16, max_fragments=1000, use_graph=True) as s:
+        tks = [s.submit(t, o, p) for t, o, (_, p) in zip(ins, outs, items)]
+        s.drain()
+        assert max(s.poll(tk)[1].batch_frames for tk in tks) <= 3
+    for t, o, (_, p) in zip(ins, outs, items):
+        assert torch.equal(o, fov.forward(t, p, layout="HWC"))
