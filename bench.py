@@ -128,6 +128,191 @@ def cpu_baseline(frame, rng_seed=99, target_s=10.0):
                       "FP64 direct 2-D, %.1f s" % (done_px, frames, spent)}
 
 
+def _spin_until(lib, target):
+    while lib.foveate_now() < target:
+        pass
+
+
+def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, seed=4, ring=8):
+    """Open-loop Poisson request traces (16 viewer sessions of mixed
+    resolution, saccade + drift gaze) replayed twice on the same GPU: once
+    through the continuous-batching server, once as plain per-frame
+    foveate_forward calls on one stream.  Latency = completion seen on the
+    host minus the scheduled arrival; frames arriving in the first warm_s
+    seconds are excluded."""
+    import ctypes
+    import torch
+    import synth
+    from paper_2012_08655_amd import _native as N, api
+    from paper_2012_08655_amd.server import Server
+
+    lib = N.lib()
+    dev = torch.device("cuda:0")
+    inputs = {}
+    for k, (h, w) in enumerate(synth.frames.RESOLUTIONS):
+        inputs[(h, w)] = torch.from_numpy(synth.grating_frame(h, w, 3, seed=20 + k)).to(dev)
+    in_desc = {key: api.tensor_desc(t, "HWC") for key, t in inputs.items()}
+    stream = torch.cuda.Stream(device=dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    legs = []
+    for ri, rate in enumerate(rates):
+        tr = synth.poisson_trace(rate, warm_s + seconds, seed=seed + ri)
+        n = len(tr["t"])
+        outs, out_desc = {}, {}
+        din, dout, prm = [], [], []
+        count = {}
+        for i in range(n):
+            s, key = int(tr["session"][i]), (int(tr["h"][i]), int(tr["w"][i]))
+            if s not in outs:
+                outs[s] = [torch.empty_like(inputs[key]) for _ in range(ring)]
+                out_desc[s] = [api.tensor_desc(o, "HWC") for o in outs[s]]
+            k = count.get(s, 0)
+            count[s] = k + 1
+            din.append(in_desc[key])
+            dout.append(out_desc[s][k % ring])
+            prm.append(N.make_params(synth.params_dict(tr["fix_x"][i], tr["fix_y"][i], 64.0, tr["slope"][i], 16.0)))
+        pixels = tr["h"] * tr["w"]
+        measured = tr["t"] >= warm_s
+        max_frag = max_batch * 8160  # 16 x 4K frames of 32x32 fragments
+        res = {"offered_fps": rate, "frames": int(measured.sum()),
+               "mean_mpix_per_frame": round(float(pixels[measured].mean()) / 1e6, 3)}
+        for mode in ("plain", "served"):
+            torch.cuda.synchronize()
+            done = np.zeros(n)
+            batch = np.zeros(n, np.int32)
+            if mode == "plain":
+                stamps = (ctypes.c_double * n)()
+                dptr = ctypes.POINTER(ctypes.c_double)
+                slots = [ctypes.cast(ctypes.addressof(stamps) + 8 * i, dptr) for i in range(n)]
+                t0 = lib.foveate_now() + 0.02
+                for i in range(n):
+                    _spin_until(lib, t0 + tr["t"][i])
+                    N.check(lib.foveate_forward(ctypes.byref(din[i]), ctypes.byref(dout[i]), ctypes.byref(prm[i]),
+                                                1, sh))
+                    N.check(lib.foveate_stream_timestamp(sh, slots[i]))
+                stream.synchronize()
+                deadline = time.time() + 10
+                while stamps[n - 1] == 0.0 and time.time() < deadline:
+                    time.sleep(0.001)
+                done[:] = np.frombuffer(stamps, dtype=np.float64)
+                batch[:] = 1
+            else:
+                srv = Server(hbm_budget_bytes=budget_mib << 20, max_batch_frames=max_batch, max_inflight_batches=2,
+                             max_requests=8192, max_fragments=max_frag, max_sigma=16.0, use_graph=True)
+                tickets = np.zeros(n, np.uint64)
+                tk = ctypes.c_uint64()
+                done_flag = ctypes.c_int32()
+                tm = N.FovTiming()
+                oldest = 0
+
+                def retire(i):
+                    N.check(lib.foveate_poll(srv._h, ctypes.c_uint64(int(tickets[i])), ctypes.byref(done_flag),
+                                             ctypes.byref(tm)))
+                    if done_flag.value:
+                        done[i] = tm.t_done
+                        batch[i] = tm.batch_frames
+                    return bool(done_flag.value)
+
+                t0 = lib.foveate_now() + 0.02
+                for i in range(n):
+                    _spin_until(lib, t0 + tr["t"][i])
+                    N.check(lib.foveate_submit(srv._h, ctypes.byref(din[i]), ctypes.byref(dout[i]),
+                                               ctypes.byref(prm[i]), ctypes.byref(tk)))
+                    tickets[i] = tk.value
+                    while oldest < i and retire(oldest):
+                        oldest += 1
+                srv.drain()
+                for i in range(oldest, n):
+                    if not retire(i):
+                        raise RuntimeError("served frame %d not done after drain" % i)
+                srv.close()
+            lat = (done - (t0 + tr["t"]))[measured] * 1e3
+            span = done[measured].max() - (t0 + tr["t"][measured].min())
+            res[mode] = {"p50_ms": round(float(np.percentile(lat, 50)), 4),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                         "max_ms": round(float(lat.max()), 4),
+                         "mpix_s": round(float(pixels[measured].sum()) / span / 1e6, 1),
+                         "mean_batch_frames": round(float(batch[measured].mean()), 3)}
+            print("bench: serving %s at %g fps: p50 %.3f ms, p99 %.3f ms" % (mode, rate, res[mode]["p50_ms"],
+                                                                          res[mode]["p99_ms"]),
+                  file=sys.stderr, flush=True)
+        legs.append(res)
+        del outs
+    return {"budget_mib": budget_mib, "max_batch_frames": max_batch, "max_inflight_batches": 2, "sessions": 16,
+            "seconds_measured": seconds, "warmup_s": warm_s, "hip_graph": True,
+            "latency": "host-seen completion minus scheduled arrival",
+            "plain": "one foveate_forward per frame on one stream at its arrival time",
+            "rates": legs}
+
+
+def _time_calls(fn, reps, stream):
+    """Median and p99 milliseconds of fn() over reps calls (HIP events on stream)."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    return float(np.median(ms)), float(np.percentile(ms, 99))
+
+
+def batch_leg(reps=10, seed=11):
+    """64 frames of mixed resolution (640x480 .. 3840x2160 RGB u8, per-frame
+    central-half fixation and slope in [0.01, 0.04]) in one autotuned launch,
+    against the same frames as 64 plain per-frame launches."""
+    import torch
+    import synth
+    import paper_2012_08655_amd as fov
+    dev = torch.device("cuda:0")
+    frames, params = synth.batch_mixed(64, seed=seed, unique_content=1)
+    ins = [torch.from_numpy(f).to(dev) for f in frames]
+    outs = [torch.empty_like(t) for t in ins]
+    stream = torch.cuda.current_stream()
+    mpix = sum(f.shape[0] * f.shape[1] for f in frames) / 1e6
+    tuned = fov.autotune_batch(ins, params, outs, layout="HWC", reps=3)
+    fov.forward_batch(ins, params, outs, layout="HWC")
+    med_b, p99_b = _time_calls(lambda: fov.forward_batch(ins, params, outs, layout="HWC"), reps, stream)
+
+    def plain():
+        for t, o, p in zip(ins, outs, params):
+            fov.forward(t, p, out=o, layout="HWC")
+
+    plain()
+    med_p, p99_p = _time_calls(plain, reps, stream)
+    return {"frames": 64, "mpix_per_batch": round(mpix, 2), "launch_config": tuned,
+            "batched": {"ms_median": round(med_b, 4), "ms_p99": round(p99_b, 4), "mpix_s": round(mpix / med_b * 1e3, 1)},
+            "plain_per_frame": {"ms_median": round(med_p, 4), "ms_p99": round(p99_p, 4),
+                                "mpix_s": round(mpix / med_p * 1e3, 1)}}
+
+
+def adjoint_leg(reps=20, seed=12):
+    """Forward and adjoint (foveate_backward) on training-style batches:
+    32 x 3x224x224 and 4 x 3x512x512 float32, fixation uniform over the image,
+    slope 0.03, cap 12, e0 32."""
+    import torch
+    import synth
+    import paper_2012_08655_amd as fov
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(seed)
+    out = []
+    for n, s in ((32, 224), (4, 512)):
+        x = torch.from_numpy(synth.uniform_frames((n, 3, s, s), seed=seed + s)).to(dev)
+        ps = [synth.params_cfg5(rng, s, s) for _ in range(n)]
+        y = fov.forward(x, ps)
+        g = torch.empty_like(y)
+        fov.backward(y, ps, grad_in=g)
+        fwd_ms, _ = _time_calls(lambda: fov.forward(x, ps, out=y), reps, stream)
+        adj_ms, _ = _time_calls(lambda: fov.backward(y, ps, grad_in=g), reps, stream)
+        mpix = n * s * s / 1e6
+        out.append({"batch": "%dx3x%dx%d f32" % (n, s, s), "forward_ms": round(fwd_ms, 4),
+                    "adjoint_ms": round(adj_ms, 4), "forward_mpix_s": round(mpix / fwd_ms * 1e3, 1),
+                    "adjoint_mpix_s": round(mpix / adj_ms * 1e3, 1)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +322,13 @@ def main():
     ap.add_argument("--distinct", type=int, default=4, help="distinct frame contents in the pool")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rates", default="120,480,1920", help="offered frames/s of the serving traces")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="measured seconds per serving trace")
+    ap.add_argument("--serve-budget-mib", type=int, default=256)
+    ap.add_argument("--serve-max-batch", type=int, default=16)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving traces")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batch and adjoint legs")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default launch configuration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain MB-sized device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -170,6 +362,11 @@ def main():
         k = i % args.pool
         fov.forward(pool_in[k], params[i], out=pool_out[k], layout="HWC", stream=stream)
 
+    tuned = None
+    if not args.no_autotune:
+        # untimed: pick the launch configuration for this workload class
+        print("bench: autotune", file=sys.stderr, flush=True)
+        tuned = fov.autotune(pool_in[0], params[0], out=pool_out[0], layout="HWC", reps=5, stream=stream)
     print("bench: warmup", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         step(i)
@@ -235,8 +432,17 @@ def main():
                      "algorithmic_flops_per_launch": float(np.mean(flops)),
                      "mean_launch_ms": round(float(kms.mean()), 5),
                      "hbm_GBs_algorithmic": round(achieved_gbs, 1)},
+        "launch_config": tuned or "default (split 1, 64 strip rows, one workgroup per queue slot)",
         "paper_context": "GTX 1060: 1.65 ms kernel for one 1920x1080 RGB frame (~1257 Mpix/s), 165 Hz with transfers",
     }
+    if not args.no_extra:
+        print("bench: batch leg", file=sys.stderr, flush=True)
+        result["batch"] = batch_leg()
+        print("bench: adjoint leg", file=sys.stderr, flush=True)
+        result["adjoint"] = adjoint_leg()
+    if not args.no_serve:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        result["serving"] = serving_leg(rates, args.serve_seconds, 0.5, args.serve_budget_mib, args.serve_max_batch)
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(distinct[0], target_s=args.cpu_seconds)

@@ -154,6 +154,67 @@ fov_status foveate_forward_batch(const fov_tensor* ins, const fov_tensor* outs, 
 fov_status foveate_backward(const fov_tensor* grad_out, const fov_tensor* grad_in,
                             const fov_params* p, int32_t np, void* stream);
 
+/* ---- launch tuning --------------------------------------------------------------------------
+ *
+ * How a forward launch maps fragments onto workgroups.  None of these choices
+ * changes a result: every output pixel sums its taps in the same order, so
+ * outputs are bitwise identical under every configuration.
+ *   split      : each fragment is cut into split x split work items (output
+ *                tiles of ceil(block / split) pixels a side, each staging its
+ *                own halo); 1, 2 or 4.  Smaller tiles give more workgroups for
+ *                small frames at the price of more halo work.
+ *   strip_rows : rows of the padded tile (halo included) staged in LDS at
+ *                once: 16, 32 or 64.  Fewer rows need less LDS per workgroup.
+ *   persistent : 1 = a grid sized to what the chip holds at once strides
+ *                over the work queue; 0 = one workgroup per queue slot.
+ *   time_us    : (output of foveate_autotune) median time of one call.
+ */
+typedef struct {
+    int32_t split, strip_rows, persistent;
+    float time_us;
+} fov_tuning;
+
+/*
+ * Autotuner.  Runs foveate_forward (or foveate_forward_batch) with every
+ * launch configuration that fits the device's LDS, `reps` timed calls each
+ * (HIP events around the whole call on `stream`; 0 = 5), and stores the
+ * fastest in the library's tuning cache under the call's workload class:
+ * device architecture and CU count, dtype pair, channels, largest fragment
+ * side, the bit length of the largest radius, the bit length of the fragment
+ * count and the frame-count class (1, 2..16, more).  Later forward calls of
+ * that class, from any thread, use the cached configuration; others use the
+ * defaults (split 1, 64 strip rows, one workgroup per queue slot).  Writes
+ * the chosen configuration to *best (may be NULL).  Arguments and errors as
+ * foveate_forward / foveate_forward_batch; `out` holds the foveated frames on
+ * return.  Synchronises `stream`.
+ */
+fov_status foveate_autotune(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
+                            int32_t reps, void* stream, fov_tuning* best);
+fov_status foveate_autotune_batch(const fov_tensor* ins, const fov_tensor* outs, const fov_params* ps,
+                                  int32_t nframes, int32_t reps, void* stream, fov_tuning* best);
+
+/*
+ * Force one configuration for the forward calls of the calling thread
+ * (tests, experiments); NULL returns the thread to the cache and defaults.
+ * FOV_EINVAL for values outside the sets above.  A forced configuration whose
+ * LDS does not fit makes the forward call fail with FOV_ERANGE.
+ */
+fov_status foveate_tuning_force(const fov_tuning* t);
+
+/* Empty the tuning cache. */
+fov_status foveate_tuning_clear(void);
+
+/* Number of entries in the tuning cache. */
+fov_status foveate_tuning_count(int32_t* n);
+
+/*
+ * Write the tuning cache to a text file (one entry per line), or merge such a
+ * file into it.  FOV_EINVAL (with the line number) for a malformed line; the
+ * cache is left unchanged then.
+ */
+fov_status foveate_tuning_save(const char* path);
+fov_status foveate_tuning_load(const char* path);
+
 /* ---- serving -------------------------------------------------------------------------------
  *
  * A request loop for frames that arrive one at a time (each with its own
@@ -220,6 +281,14 @@ fov_status foveate_submit(fov_server* s, const fov_tensor* in, const fov_tensor*
  * pending, FOV_ENOTICKET for an unknown or retired ticket.
  */
 fov_status foveate_poll(fov_server* s, uint64_t ticket, int32_t* done, fov_timing* t);
+
+/*
+ * Completion timestamp on the server clock: enqueue on `stream` a host
+ * function that stores foveate_now() into *out when the stream reaches it
+ * (used to time plain per-frame launches like served frames).  *out is host
+ * memory owned by the caller and must stay valid until then.
+ */
+fov_status foveate_stream_timestamp(void* stream, double* out);
 
 /* Block until every queued frame is done; tickets stay pollable. */
 fov_status foveate_server_drain(fov_server* s);

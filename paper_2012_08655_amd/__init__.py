@@ -18,7 +18,8 @@ def __getattr__(name):
     # The torch binding is imported lazily so that loading the C library (and
     # checking its exports) does not require torch.
     if name in ("forward", "forward_batch", "backward", "grid", "plan_device", "plan_host", "foveate", "FoveateFn",
-                "tensor_desc", "profile_begin", "profile_end"):
+                "tensor_desc", "profile_begin", "profile_end", "autotune", "autotune_batch", "tuning_force",
+                "tuning_clear", "tuning_count", "tuning_save", "tuning_load"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -42,6 +42,11 @@ class FovTiming(ctypes.Structure):
                 ("t_done", ctypes.c_double), ("batch_frames", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
+class FovTuning(ctypes.Structure):
+    _fields_ = [("split", ctypes.c_int32), ("strip_rows", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("time_us", ctypes.c_float)]
+
+
 # Every symbol declared in include/foveate.h, with (restype, argtypes).
 _TP = ctypes.POINTER(FovTensor)
 _PP = ctypes.POINTER(FovParams)
@@ -54,9 +59,19 @@ SIGNATURES = {
     "foveate_forward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
     "foveate_forward_batch": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
     "foveate_backward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
+    "foveate_autotune": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.POINTER(FovTuning)]),
+    "foveate_autotune_batch": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.POINTER(FovTuning)]),
+    "foveate_tuning_force": (ctypes.c_int, [ctypes.POINTER(FovTuning)]),
+    "foveate_tuning_clear": (ctypes.c_int, []),
+    "foveate_tuning_count": (ctypes.c_int, [_I32P]),
+    "foveate_tuning_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "foveate_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
     "foveate_profile_begin": (ctypes.c_int, [ctypes.c_int32]),
     "foveate_profile_end": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _I32P]),
     "foveate_now": (ctypes.c_double, []),
+    "foveate_stream_timestamp": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "foveate_server_create": (ctypes.c_int, [ctypes.POINTER(FovServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
     "foveate_submit": (ctypes.c_int, [ctypes.c_void_p, _TP, _TP, _PP, ctypes.POINTER(ctypes.c_uint64)]),
     "foveate_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, _I32P, ctypes.POINTER(FovTiming)]),

@@ -118,6 +118,69 @@ def forward_batch(frames, params, outs=None, layout: str = "HWC", out_dtype: tor
     return outs
 
 
+def _tuning_dict(t: N.FovTuning) -> dict:
+    return {"split": t.split, "strip_rows": t.strip_rows, "persistent": t.persistent, "time_us": t.time_us}
+
+
+def autotune(x: torch.Tensor, params, out: torch.Tensor | None = None, layout: str = "NCHW",
+             out_dtype: torch.dtype | None = None, reps: int = 5, stream=None) -> dict:
+    """Time every launch configuration on this call and cache the fastest for
+    its workload class (later forward calls of the class use it).  ``out``
+    holds the foveated result on return.  Returns the chosen configuration."""
+    if out is None:
+        out = torch.empty_like(x, dtype=out_dtype or x.dtype)
+    di, do = tensor_desc(x, layout), tensor_desc(out, layout)
+    arr, npar, _keep = _params_array(params, di.n)
+    t = N.FovTuning()
+    N.check(N.lib().foveate_autotune(ctypes.byref(di), ctypes.byref(do), arr, npar, int(reps),
+                                     _stream_handle(stream), ctypes.byref(t)))
+    return _tuning_dict(t)
+
+
+def autotune_batch(frames, params, outs, layout: str = "HWC", reps: int = 5, stream=None) -> dict:
+    """As ``autotune`` for a ``forward_batch`` call."""
+    n = len(frames)
+    di = (N.FovTensor * max(n, 1))(*[tensor_desc(f, layout) for f in frames])
+    do = (N.FovTensor * max(n, 1))(*[tensor_desc(o, layout) for o in outs])
+    arr = (N.FovParams * max(n, 1))()
+    keep = []
+    for i, p in enumerate(params):
+        a, _, k = _params_array(p, 1)
+        arr[i] = a[0]
+        keep.append(k)
+    t = N.FovTuning()
+    N.check(N.lib().foveate_autotune_batch(di, do, arr, n, int(reps), _stream_handle(stream), ctypes.byref(t)))
+    return _tuning_dict(t)
+
+
+def tuning_force(split: int | None = None, strip_rows: int = 64, persistent: int = 0):
+    """Force a launch configuration for this thread's forward calls
+    (``split=None`` returns to the cache and defaults)."""
+    if split is None:
+        N.check(N.lib().foveate_tuning_force(None))
+        return
+    t = N.FovTuning(int(split), int(strip_rows), int(persistent), 0.0)
+    N.check(N.lib().foveate_tuning_force(ctypes.byref(t)))
+
+
+def tuning_clear():
+    N.check(N.lib().foveate_tuning_clear())
+
+
+def tuning_count() -> int:
+    n = ctypes.c_int32()
+    N.check(N.lib().foveate_tuning_count(ctypes.byref(n)))
+    return n.value
+
+
+def tuning_save(path: str):
+    N.check(N.lib().foveate_tuning_save(str(path).encode()))
+
+
+def tuning_load(path: str):
+    N.check(N.lib().foveate_tuning_load(str(path).encode()))
+
+
 def backward(grad_out: torch.Tensor, params, grad_in: torch.Tensor | None = None, layout: str = "NCHW",
              stream=None) -> torch.Tensor:
     """grad_in = A^T grad_out for the same parameters as the forward."""

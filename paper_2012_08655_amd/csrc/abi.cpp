@@ -62,6 +62,10 @@ fov_status device_info(const DeviceInfo** out) {
         }
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return hip_error(e, "hipDeviceGetAttribute(CU count)");
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_error(e, "hipGetDeviceProperties");
+        std::strncpy(d.arch, prop.gcnArchName, sizeof(d.arch) - 1);
         d.lds_limit = (size_t)std::max(a, b);
         d.cus = cus;
         d.ready = true;
@@ -289,28 +293,42 @@ fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params
     return FOV_OK;
 }
 
-// One persistent forward launch over a list of frames (any shapes, one dtype
-// pair).  Up to kArgFrames descriptors travel in the kernel arguments; more
-// are uploaded as a device table from pinned memory.
-fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream) {
+CallShape call_shape(const std::vector<FrameDesc>& frames) {
+    CallShape cs;
+    for (const FrameDesc& f : frames) {
+        cs.nfrag += (int64_t)f.p.nbx * f.nby;
+        cs.r_cap = std::max(cs.r_cap, frame_r_max(f.p, f.h));
+        cs.bmax = std::max(cs.bmax, f.p.block);
+        cs.c = std::max(cs.c, f.c);
+    }
+    return cs;
+}
+
+// One forward launch over a list of frames (any shapes, one dtype pair).  Up
+// to kArgFrames descriptors travel in the kernel arguments; more are uploaded
+// as a device table from pinned memory.
+fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream,
+                       const LaunchCfg* cfg_in, bool profile) {
     fov_status s;
     const DeviceInfo* dev = nullptr;
     if ((s = device_info(&dev)) != FOV_OK) return s;
     const int nf = (int)frames.size();
     if (nf == 0) return FOV_OK;
+    const CallShape cs = call_shape(frames);
+    const LaunchCfg cfg = cfg_in ? *cfg_in : select_cfg(frames, in_dtype, out_dtype, cs);
+    const int L = cfg.split_log2;
+    if ((cs.nfrag << (2 * L)) > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
     std::vector<int32_t> prefix(nf + 1);
     int64_t total = 0;
-    int r_cap = 0, bmax = 1;
     for (int i = 0; i < nf; ++i) {
         prefix[i] = (int32_t)total;
         total += (int64_t)frames[i].p.nbx * frames[i].nby;
-        r_cap = std::max(r_cap, frame_r_max(frames[i].p, frames[i].h));
-        bmax = std::max(bmax, frames[i].p.block);
     }
-    if (total > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
     prefix[nf] = (int32_t)total;
-    const int sr = choose_strip_rows();
-    const size_t lds = forward_lds_bytes(in_dtype, r_cap, bmax, sr);
+    const int r_cap = cs.r_cap;
+    const int tile = (cs.bmax + (1 << L) - 1) >> L;
+    const int sr = cfg.strip_rows;
+    const size_t lds = forward_lds_bytes(in_dtype, r_cap, tile, sr);
     if (lds + 64 > dev->lds_limit)
         return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
                                          " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
@@ -319,10 +337,11 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     std::memset(&a, 0, sizeof(a));
     a.nframes = nf;
     a.nfrag = (int32_t)total;
+    a.split_log2 = L;
     a.r_cap = r_cap;
     a.strip_rows = sr;
     a.wstride = round_up(2 * r_cap + 1, 16);
-    a.nslots = queue_slots(a.nfrag, r_cap);
+    a.nslots = queue_slots(a.nfrag << (2 * L), r_cap);
     const size_t pbytes = (plan_bytes(a.nfrag, a.nslots, a.wstride, wsize) + 255) / 256 * 256;
     const bool upload = nf > kArgFrames;
     const size_t tbytes = ((size_t)nf * sizeof(FrameDesc) + (size_t)(nf + 1) * 4 + 255) / 256 * 256;
@@ -352,13 +371,13 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
         for (int i = 0; i <= nf; ++i) a.kprefix[i] = prefix[i];
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (g_prof.on && g_prof.used < g_prof.ev.size()) {
+    if (profile && g_prof.on && g_prof.used < g_prof.ev.size()) {
         e0 = g_prof.ev[g_prof.used].first;
         e1 = g_prof.ev[g_prof.used].second;
         ++g_prof.used;
     }
-    return launch_forward(a, in_dtype, out_dtype, lds, plan, stream, dev->lds_limit, dev->cus, dispatch_persistent(),
-                          e0, e1);
+    return launch_forward(a, in_dtype, out_dtype, lds, plan, stream, dev->lds_limit, dev->cus, cfg.persistent, e0,
+                          e1);
 }
 
 FrameDesc make_frame_desc(const fov_tensor& in, const fov_tensor& out, int n, const fov_params& p) {
@@ -372,6 +391,52 @@ FrameDesc make_frame_desc(const fov_tensor& in, const fov_tensor& out, int n, co
     d.p = to_frame(p, in.h, in.w);
     d.nby = grid_extent(in.h, p.origin_y, p.block);
     return d;
+}
+
+fov_status collect_single(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
+                          std::vector<FrameDesc>* frames, int* dt_in, int* dt_out) {
+    bool empty = false;
+    fov_status s = prepare(in, out, p, np, false, &empty);
+    frames->clear();
+    if (s != FOV_OK || empty) return s;
+    frames->reserve(in->n);
+    for (int i = 0; i < in->n; ++i) frames->push_back(make_frame_desc(*in, *out, i, p[np == 1 ? 0 : i]));
+    *dt_in = in->dtype;
+    *dt_out = out->dtype;
+    return FOV_OK;
+}
+
+fov_status collect_batch(const fov_tensor* ins, const fov_tensor* outs, const fov_params* ps, int32_t nframes,
+                         std::vector<FrameDesc>* frames, int* dt_in, int* dt_out) {
+    frames->clear();
+    if (nframes < 0) return set_error(FOV_EINVAL, "nframes < 0");
+    if (nframes == 0) return FOV_OK;
+    if (!ins || !outs || !ps) return set_error(FOV_EINVAL, "NULL argument");
+    frames->reserve(nframes);
+    *dt_in = *dt_out = -1;
+    for (int i = 0; i < nframes; ++i) {
+        bool empty = false;
+        fov_status s = prepare(&ins[i], &outs[i], &ps[i], 1, false, &empty);
+        if (s != FOV_OK) return set_error(s, "frame " + std::to_string(i) + ": " + last_error());
+        if (empty) continue;
+        if (ins[i].n != 1) return set_error(FOV_EINVAL, "frame " + std::to_string(i) + ": each view must hold one frame");
+        if (*dt_in < 0) { *dt_in = ins[i].dtype; *dt_out = outs[i].dtype; }
+        if (ins[i].dtype != *dt_in || outs[i].dtype != *dt_out)
+            return set_error(FOV_EDTYPE, "all frames of a batch must share one dtype pair");
+        frames->push_back(make_frame_desc(ins[i], outs[i], 0, ps[i]));
+    }
+    // outputs of different frames must not overlap inputs of others either
+    for (int i = 0; i < nframes; ++i)
+        for (int j = 0; j < nframes; ++j) {
+            if (i == j || is_empty(ins[j]) || is_empty(outs[i])) continue;
+            fov_status s = check_alias(ins[j], outs[i]);
+            if (s != FOV_OK) return set_error(s, "output of frame " + std::to_string(i) + " overlaps input of frame " + std::to_string(j));
+            if (j < i) {
+                s = check_alias(outs[j], outs[i]);
+                if (s != FOV_OK) return set_error(s, "outputs of frames " + std::to_string(j) + " and " + std::to_string(i) + " overlap");
+            }
+        }
+    return FOV_OK;
 }
 
 }  // namespace fov
@@ -459,45 +524,19 @@ fov_status foveate_plan(int32_t h, int32_t w, const fov_params* p, double* sigma
 
 fov_status foveate_forward(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
                            void* stream) {
-    bool empty = false;
-    fov_status s = prepare(in, out, p, np, false, &empty);
-    if (s != FOV_OK || empty) return s;
     std::vector<FrameDesc> frames;
-    frames.reserve(in->n);
-    for (int i = 0; i < in->n; ++i) frames.push_back(make_frame_desc(*in, *out, i, p[np == 1 ? 0 : i]));
-    return run_forward(frames, in->dtype, out->dtype, (hipStream_t)stream);
+    int dt_in = 0, dt_out = 0;
+    fov_status s = collect_single(in, out, p, np, &frames, &dt_in, &dt_out);
+    if (s != FOV_OK || frames.empty()) return s;
+    return run_forward(frames, dt_in, dt_out, (hipStream_t)stream);
 }
 
 fov_status foveate_forward_batch(const fov_tensor* ins, const fov_tensor* outs, const fov_params* ps,
                                  int32_t nframes, void* stream) {
-    if (nframes < 0) return set_error(FOV_EINVAL, "nframes < 0");
-    if (nframes == 0) return FOV_OK;
-    if (!ins || !outs || !ps) return set_error(FOV_EINVAL, "NULL argument");
     std::vector<FrameDesc> frames;
-    frames.reserve(nframes);
-    int dt_in = -1, dt_out = -1;
-    for (int i = 0; i < nframes; ++i) {
-        bool empty = false;
-        fov_status s = prepare(&ins[i], &outs[i], &ps[i], 1, false, &empty);
-        if (s != FOV_OK) return set_error(s, "frame " + std::to_string(i) + ": " + last_error());
-        if (empty) continue;
-        if (ins[i].n != 1) return set_error(FOV_EINVAL, "frame " + std::to_string(i) + ": each view must hold one frame");
-        if (dt_in < 0) { dt_in = ins[i].dtype; dt_out = outs[i].dtype; }
-        if (ins[i].dtype != dt_in || outs[i].dtype != dt_out)
-            return set_error(FOV_EDTYPE, "all frames of a batch must share one dtype pair");
-        frames.push_back(make_frame_desc(ins[i], outs[i], 0, ps[i]));
-    }
-    // outputs of different frames must not overlap inputs of others either
-    for (int i = 0; i < nframes; ++i)
-        for (int j = 0; j < nframes; ++j) {
-            if (i == j || is_empty(ins[j]) || is_empty(outs[i])) continue;
-            fov_status s = check_alias(ins[j], outs[i]);
-            if (s != FOV_OK) return set_error(s, "output of frame " + std::to_string(i) + " overlaps input of frame " + std::to_string(j));
-            if (j < i) {
-                s = check_alias(outs[j], outs[i]);
-                if (s != FOV_OK) return set_error(s, "outputs of frames " + std::to_string(j) + " and " + std::to_string(i) + " overlap");
-            }
-        }
+    int dt_in = 0, dt_out = 0;
+    fov_status s = collect_batch(ins, outs, ps, nframes, &frames, &dt_in, &dt_out);
+    if (s != FOV_OK || frames.empty()) return s;
     return run_forward(frames, dt_in, dt_out, (hipStream_t)stream);
 }
 

@@ -20,11 +20,12 @@ constexpr int kArgFrames = 16;
 
 // Kernel arguments shared by the plan, order and main forward kernels.
 // Fragments of all frames are numbered consecutively: frame f owns fragments
-// [prefix[f], prefix[f+1]).
+// [prefix[f], prefix[f+1]).  Work item i belongs to fragment i >> (2 split_log2).
 struct FwdLaunch {
     int32_t nframes, nfrag;
-    int32_t nslots;      // queue slots (fragments plus empty padding slots)
-    int32_t pad0_;
+    int32_t nslots;      // queue slots (work items plus empty padding slots)
+    int32_t split_log2;  // each fragment is cut into (2^split_log2)^2 work items (output tiles of
+                         // ceil(B / 2^split_log2) pixels a side); 0 = one item per fragment
     int32_t r_cap;       // largest radius the LDS allocation was sized for
     int32_t strip_rows;  // padded-tile rows staged in LDS at once
     int32_t wstride;     // weights per fragment in the plan workspace (multiple of 16)
@@ -49,11 +50,12 @@ struct BatchHeader {
 struct PlanBuffers {
     int32_t* radius;   // [nfrag] radius of each fragment
     int32_t* okey;     // [nfrag] (ring, angle bin) cell of each fragment for the queue order
-    int32_t* order;    // [nslots] queue: fragment ids (-1 = empty slot), see the order kernel
+    int32_t* order;    // [nslots] queue: work item ids (-1 = empty slot), see the order kernel
     void* weights;     // [nfrag][wstride] normalised taps, float (u8/f32) or double (f64)
 };
 
-int queue_slots(int nfrag, int r_cap);
+// Queue slots for nitems work items.
+int queue_slots(int nitems, int r_cap);
 size_t plan_bytes(int nfrag, int nslots, int wstride, int wsize);
 PlanBuffers carve_plan(void* ws, int nfrag, int nslots);
 
@@ -69,8 +71,13 @@ fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_
 // Device plan for foveate_plan(): sigma and radius of every fragment.
 fov_status launch_plan(const FrameParams& fp, int nblk, double* sigma_out, int32_t* r_out, hipStream_t stream);
 
-// LDS bytes a forward workgroup needs for radius r_cap and fragment side B.
-size_t forward_lds_bytes(int in_dtype, int r_cap, int B, int strip_rows);
+// LDS bytes a forward workgroup needs for radius r_cap and output tiles of
+// side `tile` (the fragment side B divided by the split, rounded up).
+size_t forward_lds_bytes(int in_dtype, int r_cap, int tile, int strip_rows);
+
+// Padded-tile rows of a tile of side `tile` at radius r (what a strip height
+// above it cannot change).
+int forward_tile_rows(int r, int tile);
 
 // Largest strip height the kernel stages at once.
 int forward_strip_max();

@@ -22,7 +22,8 @@
 //     operands of the FMAs.  A fragment with r = 0 is copied.
 //
 // Every output sums its taps in the same order (k = -r .. r) whatever the
-// strip height, so results do not depend on tuning choices.
+// strip height, output tile split or dispatch mode, so results do not depend
+// on tuning choices.
 #include "forward.h"
 
 #include <hip/hip_runtime.h>
@@ -403,6 +404,24 @@ __device__ __forceinline__ Frag describe(const FrameDesc* __restrict__ table, co
     return describe_at(table + f, prefix[f], gid);
 }
 
+// Narrow a fragment to output tile `sub` of its L-level split: tiles of
+// T = ceil(B / 2^L) pixels a side, row-major, clipped to the fragment and the
+// frame.  Returns false for a tile that holds no pixel (ragged splits).
+__device__ __forceinline__ bool narrow_to_tile(Frag& F, int L, int sub) {
+    if (L == 0) return true;
+    const FrameParams& fp = F.fd->p;
+    const int B = fp.block, T = (B + (1 << L) - 1) >> L;
+    const int sx = sub & ((1 << L) - 1), sy = sub >> L;
+    const int X0 = fp.origin_x + F.bx * B, Y0 = fp.origin_y + F.by * B;
+    const int x0 = X0 + sx * T, y0 = Y0 + sy * T;
+    const int x1 = min(min(x0 + T, X0 + B), F.fd->w), y1 = min(min(y0 + T, Y0 + B), F.fd->h);
+    F.xa = max(x0, 0);
+    F.ya = max(y0, 0);
+    F.bw = x1 - F.xa;
+    F.bh = y1 - F.ya;
+    return F.bw > 0 && F.bh > 0;
+}
+
 // Foveal fragment: copied (Appendix "Workload of the Block").
 template <typename TIn, typename TOut>
 __device__ __forceinline__ void copy_fragment(const Frag& F) {
@@ -492,8 +511,9 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
     }
 }
 
-// Fragments are taken from the queue (fragment ids by decreasing radius, so
-// the costliest start first).  PERSIST = false: one workgroup per queue slot,
+// Work items are taken from the queue (by decreasing radius, so the costliest
+// start first); an item is a whole fragment or, with a split, one output tile
+// of it (same radius and taps, its own halo).  PERSIST = false: one workgroup per queue slot,
 // the hardware dispatcher hands slots out in order as workgroups retire.
 // PERSIST = true: a grid sized to what the chip holds at once; workgroup b
 // takes slots b, b + grid, b + 2 grid, ... (round-robin over the cost-sorted
@@ -507,14 +527,20 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
     extern __shared__ __align__(16) unsigned char smem[];
     const int nslots = a.hdr ? a.hdr[2] : a.nslots;
     const int nframes = a.hdr ? a.hdr[0] : a.nframes;
+    const int L = a.split_log2;
     for (int q = blockIdx.x; q < nslots; q += gridDim.x) {
-        const int gid = order[q];
-        if (gid < 0) {  // empty slot
+        const int item = order[q];
+        if (item < 0) {  // empty slot
             if (!PERSIST) break;
             continue;
         }
+        const int gid = item >> (2 * L);
         const int r = radius[gid];
-        const Frag F = describe(table, prefix, nframes, gid);
+        Frag F = describe(table, prefix, nframes, gid);
+        if (!narrow_to_tile(F, L, item & ((1 << (2 * L)) - 1))) {
+            if (!PERSIST) break;
+            continue;
+        }
         process_fragment<TIn, TOut, TS, TC>(a, gid, r, F, wts, smem);
         if (!PERSIST) break;
         __syncthreads();  // this fragment's LDS reads are done before the next one is staged
@@ -609,8 +635,9 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
     }
 }
 
-// Queue order.  Fragments go by decreasing radius (their cost grows with r), so
-// the costliest start first and the launch does not end on a long tail.
+// Queue order.  Work items go by decreasing radius (their cost grows with r),
+// so the costliest start first and the launch does not end on a long tail.
+// The items of a split fragment share its (ring, angle bin) cell.
 // Workgroup q runs on XCD q mod 8 (the dispatcher deals workgroups to the
 // eight XCDs in turn), and each XCD has its own L2: neighbouring fragments
 // share halo rows, so within every radius ring the fragments are sorted by
@@ -623,10 +650,10 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
 // depend on it.
 
 __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t* __restrict__ okey, int n_arg,
-                                                                  int nrings, int nang, int nslots_arg,
+                                                                  int L, int nrings, int nang, int nslots_arg,
                                                                   const int32_t* __restrict__ hdr,
                                                                   int32_t* __restrict__ order) {
-    const int n = hdr ? hdr[1] : n_arg;
+    const int n = (hdr ? hdr[1] : n_arg) << (2 * L);  // work items
     const int nslots = hdr ? hdr[2] : nslots_arg;
     __shared__ int cells[kOrderCells];        // [ring][angle bin], ring 0 = largest radius
     __shared__ int ring_n[kOrderMaxRings];    // fragments per ring
@@ -636,7 +663,7 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
     const int ncell = nrings * nang;
     for (int i = tid; i < ncell; i += kOrderThreads) cells[i] = 0;
     __syncthreads();
-    for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&cells[okey[i]], 1);
+    for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&cells[okey[i >> (2 * L)]], 1);
     __syncthreads();
     // exclusive scan of the angle bins inside each ring (one wave per ring)
     for (int ring = wave; ring < nrings; ring += kOrderThreads / 64) {
@@ -673,7 +700,7 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
     }
     __syncthreads();
     for (int i = tid; i < n; i += kOrderThreads) {
-        const int key = okey[i];
+        const int key = okey[i >> (2 * L)];
         const int ring = key / nang;
         const int j = atomicAdd(&cells[key], 1);  // rank in the ring
         const int m = ring_n[ring];
@@ -763,7 +790,7 @@ fov_status launch_typed(const FwdLaunch& a, size_t lds, const PlanBuffers& plan,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "plan kernel launch");
     hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.okey, a.nfrag,
-                       nrings, nang, a.nslots, a.hdr, plan.order);
+                       a.split_log2, nrings, nang, a.nslots, a.hdr, plan.order);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "order kernel launch");
     if (persist || a.hdr) return launch_main<TIn, TOut, TS, TC, true>(a, lds, plan, stream, lds_limit, cus, ev_start, ev_stop);
@@ -775,7 +802,7 @@ int compute_size(int in_dtype) { return in_dtype == FOV_F64 ? 8 : 4; }
 
 }  // namespace
 
-int queue_slots(int nfrag, int r_cap) { return nfrag + kXcds * order_rings(r_cap); }
+int queue_slots(int nitems, int r_cap) { return nitems + kXcds * order_rings(r_cap); }
 
 size_t plan_bytes(int nfrag, int nslots, int wstride, int wsize) {
     return 2 * align16((size_t)nfrag * 4) + align16((size_t)nslots * 4) + 256 + (size_t)nfrag * wstride * wsize;
@@ -794,8 +821,10 @@ PlanBuffers carve_plan(void* ws, int nfrag, int nslots) {
 
 int forward_strip_max() { return kStripMax; }
 
-size_t forward_lds_bytes(int in_dtype, int r_cap, int B, int strip_rows) {
-    const Geom g = geom(r_cap, B, B);
+int forward_tile_rows(int r, int tile) { return geom(r, tile, tile).TH; }
+
+size_t forward_lds_bytes(int in_dtype, int r_cap, int tile, int strip_rows) {
+    const Geom g = geom(r_cap, tile, tile);
     int rows = strip_rows < g.TH ? strip_rows : g.TH;
     if (rows > kStripMax) rows = kStripMax;
     const int es = stage_size(in_dtype), ec = compute_size(in_dtype);

@@ -15,6 +15,7 @@ struct DeviceInfo {
     bool ready = false;
     size_t lds_limit = 0;  // dynamic LDS one workgroup may use
     int cus = 0;
+    char arch[64] = {0};   // gcnArchName, e.g. "gfx950:sramecc+:xnack-"
 };
 fov_status device_info(const DeviceInfo** out);
 
@@ -43,12 +44,39 @@ int frame_r_max(const FrameParams& f, int h);
 int choose_strip_rows();
 bool dispatch_persistent();
 
+// Launch configuration of the forward kernel (public form: fov_tuning).
+struct LaunchCfg {
+    int split_log2 = 0;
+    int strip_rows = 64;
+    bool persistent = false;
+};
+
+// What a forward call launches: largest radius and fragment side, fragments.
+struct CallShape {
+    int r_cap = 0, bmax = 1, c = 1;
+    int64_t nfrag = 0;
+};
+CallShape call_shape(const std::vector<FrameDesc>& frames);
+
+// Configuration for a call: the thread's forced one, else the tuning cache's
+// entry for the call's class, else the defaults.
+LaunchCfg select_cfg(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, const CallShape& cs);
+
 // Validation of a forward (or backward) call's views and parameters.
 fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np, bool backward,
                    bool* empty);
 // Descriptor of frame n of a validated (in, out) pair.
 FrameDesc make_frame_desc(const fov_tensor& in, const fov_tensor& out, int n, const fov_params& p);
-// Plan, order and main kernels for a list of frames on `stream`.
-fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream);
+// Argument checks of foveate_forward / foveate_forward_batch, producing the
+// frame list (empty frames dropped) and the dtype pair.
+fov_status collect_single(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np,
+                          std::vector<FrameDesc>* frames, int* dt_in, int* dt_out);
+fov_status collect_batch(const fov_tensor* ins, const fov_tensor* outs, const fov_params* ps, int32_t nframes,
+                         std::vector<FrameDesc>* frames, int* dt_in, int* dt_out);
+// Plan, order and main kernels for a list of frames on `stream`, with the
+// given configuration (NULL: select_cfg).  profile: take the thread's
+// profiler events, if any, for the main kernel.
+fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream,
+                       const LaunchCfg* cfg = nullptr, bool profile = true);
 
 }  // namespace fov

@@ -332,9 +332,22 @@ void release(ServerImpl* s) {
 }  // namespace
 }  // namespace fov
 
+namespace fov {
+namespace {
+void store_now(void* p) { *static_cast<double*>(p) = now_s(); }
+}  // namespace
+}  // namespace fov
+
 extern "C" {
 
 double foveate_now(void) { return now_s(); }
+
+fov_status foveate_stream_timestamp(void* stream, double* out) {
+    if (!out) return set_error(FOV_EINVAL, "out is NULL");
+    hipError_t e = hipLaunchHostFunc((hipStream_t)stream, store_now, out);
+    if (e != hipSuccess) return hip_error(e, "hipLaunchHostFunc");
+    return FOV_OK;
+}
 
 fov_status foveate_server_create(const fov_server_cfg* cfg, fov_server** out) {
     if (!cfg || !out) return set_error(FOV_EINVAL, "NULL argument");
