@@ -56,7 +56,7 @@ def algorithmic_fma(h, w, c, p, plan_r):
 
 
 KERNEL_SOURCES = ("paper_2012_08655_amd/csrc/forward.hip", "paper_2012_08655_amd/csrc/forward.h",
-                  "paper_2012_08655_amd/csrc/common.h")
+                  "paper_2012_08655_amd/csrc/conv.h", "paper_2012_08655_amd/csrc/common.h")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fov_fwd_u8_1080p_rgb_traffic.md")
 
 

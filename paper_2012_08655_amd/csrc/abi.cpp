@@ -293,6 +293,37 @@ fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params
     return FOV_OK;
 }
 
+size_t frame_table_bytes(int nf) { return ((size_t)nf * sizeof(FrameDesc) + (size_t)(nf + 1) * 4 + 255) / 256 * 256; }
+
+// Place a launch's frame descriptors where its kernels read them: in the
+// kernel arguments (up to kArgFrames; the plan kernel copies them to dtab) or
+// uploaded to dtab from the workspace's pinned buffer.
+fov_status stage_frame_table(const FrameDesc* frames, int nf, const int32_t* prefix, Workspace* ws, char* dtab,
+                             size_t tbytes, hipStream_t stream, FwdLaunch* a) {
+    a->table = reinterpret_cast<FrameDesc*>(dtab);
+    a->prefix = reinterpret_cast<int32_t*>(dtab + (size_t)nf * sizeof(FrameDesc));
+    if (nf > kArgFrames) {
+        if (ws->upload_pending) {
+            hipError_t e = hipEventSynchronize(ws->upload_done);
+            if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(upload)");
+            ws->upload_pending = false;
+        }
+        char* hst = static_cast<char*>(ws->host);
+        std::memcpy(hst, frames, (size_t)nf * sizeof(FrameDesc));
+        std::memcpy(hst + (size_t)nf * sizeof(FrameDesc), prefix, (size_t)(nf + 1) * 4);
+        hipError_t e = hipMemcpyAsync(dtab, hst, tbytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(frame table)");
+        e = hipEventRecord(ws->upload_done, stream);
+        if (e != hipSuccess) return hip_error(e, "hipEventRecord(upload)");
+        ws->upload_pending = true;
+    } else {
+        a->from_args = 1;
+        for (int i = 0; i < nf; ++i) a->fr[i] = frames[i];
+        for (int i = 0; i <= nf; ++i) a->kprefix[i] = prefix[i];
+    }
+    return FOV_OK;
+}
+
 CallShape call_shape(const std::vector<FrameDesc>& frames) {
     CallShape cs;
     for (const FrameDesc& f : frames) {
@@ -344,32 +375,13 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     a.nslots = queue_slots(a.nfrag << (2 * L), r_cap);
     const size_t pbytes = (plan_bytes(a.nfrag, a.nslots, a.wstride, wsize) + 255) / 256 * 256;
     const bool upload = nf > kArgFrames;
-    const size_t tbytes = ((size_t)nf * sizeof(FrameDesc) + (size_t)(nf + 1) * 4 + 255) / 256 * 256;
+    const size_t tbytes = frame_table_bytes(nf);
     Workspace* ws = nullptr;
     if ((s = workspace(stream, pbytes + tbytes, upload ? tbytes : 0, &ws)) != FOV_OK) return s;
     const PlanBuffers plan = carve_plan(ws->dev, a.nfrag, a.nslots);
-    char* dtab = static_cast<char*>(ws->dev) + pbytes;
-    a.table = reinterpret_cast<FrameDesc*>(dtab);
-    a.prefix = reinterpret_cast<int32_t*>(dtab + (size_t)nf * sizeof(FrameDesc));
-    if (upload) {
-        if (ws->upload_pending) {
-            hipError_t e = hipEventSynchronize(ws->upload_done);
-            if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(upload)");
-            ws->upload_pending = false;
-        }
-        char* hst = static_cast<char*>(ws->host);
-        std::memcpy(hst, frames.data(), (size_t)nf * sizeof(FrameDesc));
-        std::memcpy(hst + (size_t)nf * sizeof(FrameDesc), prefix.data(), (size_t)(nf + 1) * 4);
-        hipError_t e = hipMemcpyAsync(dtab, hst, tbytes, hipMemcpyHostToDevice, stream);
-        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(frame table)");
-        e = hipEventRecord(ws->upload_done, stream);
-        if (e != hipSuccess) return hip_error(e, "hipEventRecord(upload)");
-        ws->upload_pending = true;
-    } else {
-        a.from_args = 1;
-        for (int i = 0; i < nf; ++i) a.fr[i] = frames[i];
-        for (int i = 0; i <= nf; ++i) a.kprefix[i] = prefix[i];
-    }
+    if ((s = stage_frame_table(frames.data(), nf, prefix.data(), ws, static_cast<char*>(ws->dev) + pbytes, tbytes,
+                               stream, &a)) != FOV_OK)
+        return s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile && g_prof.on && g_prof.used < g_prof.ev.size()) {
         e0 = g_prof.ev[g_prof.used].first;
@@ -378,6 +390,82 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     }
     return launch_forward(a, in_dtype, out_dtype, lds, plan, stream, dev->lds_limit, dev->cus, cfg.persistent, e0,
                           e1);
+}
+
+// Scratch of the adjoint's horizontal transposes, per launch: frames are
+// processed in groups whose scratch stays below this (one frame at least).
+constexpr size_t kAdjScratchMax = (size_t)256 << 20;
+
+// Adjoint of one frame group on `stream`: plan, horizontal transpose, vertical gather.
+fov_status run_backward_group(const FrameDesc* frames, int nf, int dtype, hipStream_t stream) {
+    fov_status s;
+    const DeviceInfo* dev = nullptr;
+    if ((s = device_info(&dev)) != FOV_OK) return s;
+    const std::vector<FrameDesc> fl(frames, frames + nf);
+    const CallShape cs = call_shape(fl);
+    const int es = dtype == FOV_F64 ? 8 : 4;
+    const AdjShape sh = adjoint_shape(es, cs.r_cap, cs.bmax, cs.c);
+    std::vector<int32_t> prefix(nf + 1);
+    int64_t total = 0;
+    for (int i = 0; i < nf; ++i) {
+        prefix[i] = (int32_t)total;
+        total += (int64_t)fl[i].p.nbx * fl[i].nby;
+    }
+    prefix[nf] = (int32_t)total;
+    if (total > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
+    FwdLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.nframes = nf;
+    a.nfrag = (int32_t)total;
+    a.r_cap = cs.r_cap;
+    a.wstride = round_up(2 * cs.r_cap + 1 + kAdjWeightLead, 16);
+    const size_t f4 = ((size_t)a.nfrag * 4 + 255) / 256 * 256;
+    const size_t wbytes = (((size_t)kAdjWeightLead + (size_t)a.nfrag * a.wstride) * es + 255) / 256 * 256;
+    const size_t tbytes = frame_table_bytes(nf);
+    const size_t sbytes = adjoint_scratch_elems(sh, a.nfrag) * es;
+    Workspace* ws = nullptr;
+    if ((s = workspace(stream, 2 * f4 + wbytes + tbytes + sbytes, nf > kArgFrames ? tbytes : 0, &ws)) != FOV_OK)
+        return s;
+    char* base = static_cast<char*>(ws->dev);
+    PlanBuffers plan;
+    plan.radius = reinterpret_cast<int32_t*>(base);
+    plan.okey = reinterpret_cast<int32_t*>(base + f4);
+    plan.order = nullptr;
+    char* wbase = base + 2 * f4;
+    plan.weights = wbase + (size_t)kAdjWeightLead * es;
+    char* dtab = wbase + wbytes;
+    void* scratch = dtab + tbytes;
+    if ((s = stage_frame_table(fl.data(), nf, prefix.data(), ws, dtab, tbytes, stream, &a)) != FOV_OK) return s;
+    return launch_adjoint(a, sh, es, plan, wbase, scratch, stream, dev->lds_limit);
+}
+
+fov_status run_backward(const fov_tensor* go, const fov_tensor* gi, const fov_params* p, int32_t np,
+                        hipStream_t stream) {
+    std::vector<FrameDesc> frames;
+    frames.reserve(go->n);
+    for (int i = 0; i < go->n; ++i) frames.push_back(make_frame_desc(*go, *gi, i, p[np == 1 ? 0 : i]));
+    const int es = go->dtype == FOV_F64 ? 8 : 4;
+    size_t f0 = 0;
+    while (f0 < frames.size()) {
+        size_t f1 = f0 + 1;
+        CallShape cs = call_shape({frames[f0]});
+        while (f1 < frames.size()) {
+            const CallShape one = call_shape({frames[f1]});
+            CallShape m = cs;
+            m.r_cap = std::max(m.r_cap, one.r_cap);
+            m.bmax = std::max(m.bmax, one.bmax);
+            m.c = std::max(m.c, one.c);
+            m.nfrag += one.nfrag;
+            const AdjShape sh = adjoint_shape(es, m.r_cap, m.bmax, m.c);
+            if (m.nfrag > (1 << 30) || adjoint_scratch_elems(sh, (int)m.nfrag) * es > kAdjScratchMax) break;
+            cs = m;
+            ++f1;
+        }
+        fov_status s = run_backward_group(frames.data() + f0, (int)(f1 - f0), go->dtype, stream);
+        if (s != FOV_OK) return s;
+        f0 = f1;
+    }
+    return FOV_OK;
 }
 
 FrameDesc make_frame_desc(const fov_tensor& in, const fov_tensor& out, int n, const fov_params& p) {
@@ -545,9 +633,7 @@ fov_status foveate_backward(const fov_tensor* grad_out, const fov_tensor* grad_i
     bool empty = false;
     fov_status s = prepare(grad_out, grad_in, p, np, true, &empty);
     if (s != FOV_OK || empty) return s;
-    const DeviceInfo* dev = nullptr;
-    if ((s = device_info(&dev)) != FOV_OK) return s;
-    return launch_adjoint_all(grad_out, grad_in, p, np, (hipStream_t)stream, dev->lds_limit);
+    return run_backward(grad_out, grad_in, p, np, (hipStream_t)stream);
 }
 
 }  // extern "C"

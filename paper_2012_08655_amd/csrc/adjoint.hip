@@ -1,165 +1,246 @@
 // Adjoint of block-wise foveation (the backward pass for training through the
-// foveation), as a gather: no atomics, each output element written once.
+// foveation), as a gather: no atomics, every element written once, a fixed
+// summation order.
 //
-// The forward map restricted to one fragment b is separable with clamp-folded
-// 1-D weights: along an axis of length L, output p reads input q with weight
-//     a_b(p, q) = sum over taps i in [-r_b, r_b] with clamp(p + i, 0, L-1) = q
-//                 of w_b(i)
-// (interior q: w_b(q - p); q = 0 collects every tap at or below the edge;
-// q = L-1 every tap at or above it).  Hence
-//     grad_in(qy, qx) = sum_b sum_{p in b} a_b(py, qy) a_b(px, qx) grad_out(py, px).
-// A workgroup owns one tile of grad_in (aligned with the fragment grid) and
-// visits every fragment whose reach [p_lo - r_b, p_hi + r_b] overlaps it;
-// per fragment it forms the two small folded-weight matrices in LDS and
-// applies them as a horizontal then a vertical contraction.
+// Restricted to one fragment b, the forward map is separable: a horizontal
+// then a vertical 1-D correlation with b's taps w_b over the clamped frame.
+// Its transpose maps the fragment's output gradient g_b back over b's
+// padded window, so
+//     grad_in = sum_b Fold_y V_b^T Fold_x H_b^T g_b,
+// where H_b^T / V_b^T correlate with w_b (the taps are symmetric) over the
+// fragment's rows / columns padded by r_b, and Fold adds what lands outside
+// the frame onto the edge row or column (the transpose of clamp-to-edge).
+// On an axis of length L the fold gives output 0 the extra weight
+// cdf_b(-p-1) = sum_{i <= -p-1} w_b(i) for input p, and output L-1 the extra
+// weight cdf_b(p-L).
+//
+// Two kernels after the plan kernel (radius and taps of every fragment):
+//  1. fov_adj_h_kernel — one workgroup per fragment: the horizontal transpose
+//     Fold_x H_b^T g_b (rows of b, columns of b's reach) into a scratch buffer.
+//     Lanes take rows; a wave shares one group of 8 output columns, so the
+//     taps that meet the fragment form one wave-uniform range.
+//  2. fov_adj_v_kernel — one workgroup per output tile (the fragment grid):
+//     for every fragment b whose reach meets the tile, stage b's scratch rows
+//     over the tile's columns (zero-padded) in LDS and accumulate the vertical
+//     transpose in registers; the fragments are visited in a fixed order.
+// Both passes are the forward's register-window correlations with the taps
+// read as scalar operands, run over the band of taps that meet the fragment.
 #include "adjoint.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstring>
 
+#include "conv.h"
 
 namespace fov {
 
 namespace {
 
-__device__ double block_sum_d(double v, double* red) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int i = 0; i < kThreads / 64; ++i) s += red[i];
-    __syncthreads();
-    return s;
+constexpr int kPadA = 12;  // zero columns staged before a fragment row (horizontal kernel)
+constexpr int kAdjTasks = (kMaxBlock * (kMaxBlock / kPV) + kThreads - 1) / kThreads;
+
+__global__ void fov_adj_lead_kernel(unsigned char* p, int bytes) {
+    for (int i = threadIdx.x; i < bytes; i += blockDim.x) p[i] = 0;
 }
 
-// Folded weight a(p, q) on an axis of length L; cdf[k] = sum_{m<=k} wtab[m],
-// tap index m = i + r.
-__device__ __forceinline__ double folded(int p, int q, int r, int L, const double* wtab, const double* cdf) {
-    if (L == 1) return cdf[2 * r];
-    if (q > 0 && q < L - 1) {
-        const int d = q - p;
-        return (d >= -r && d <= r) ? wtab[d + r] : 0.0;
-    }
-    if (q == 0) {
-        const int hi = -p;  // taps i <= -p land on the edge
-        if (hi < -r) return 0.0;
-        return cdf[min(hi, r) + r];
-    }
-    const int lo = max(L - 1 - p, -r);  // q == L-1: taps i >= L-1-p
-    if (lo > r) return 0.0;
-    return cdf[2 * r] - (lo - 1 + r >= 0 ? cdf[lo - 1 + r] : 0.0);
-}
-
-constexpr int kMaxOut = (kMaxBlock * kMaxBlock + kThreads - 1) / kThreads;
-
+// Horizontal transpose of fragment gid into scratch[gid][c][row][x - xa + r_cap]
+// for the columns x of its clamped reach.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fov_adj_kernel(const AdjLaunch a) {
+__global__ __launch_bounds__(kThreads) void fov_adj_h_kernel(const FwdLaunch a, const AdjShape s,
+                                                             const FrameDesc* __restrict__ table,
+                                                             const int32_t* __restrict__ prefix,
+                                                             const int32_t* __restrict__ radius,
+                                                             const T* __restrict__ wts, T* __restrict__ scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
+    T* rows = reinterpret_cast<T*>(smem);  // [chunk_c * bh][pitch_a]
+    constexpr int V = 16 / sizeof(T);      // elements per aligned 16-byte LDS load
     const int gid = blockIdx.x;
-    int f = 0;
-    while (f + 1 < a.nframes && gid >= a.blk_prefix[f + 1]) ++f;
-    const FrameParams& fp = a.fr[f];
-    const int B = fp.block;
-    const int nbx = fp.nbx, nby = grid_extent(a.h, fp.origin_y, B);
-    const int lq = gid - a.blk_prefix[f];
-    const int byq = lq / nbx, bxq = lq - byq * nbx;
-    const int qx0 = max(fp.origin_x + bxq * B, 0), qy0 = max(fp.origin_y + byq * B, 0);
-    const int qw = min(fp.origin_x + (bxq + 1) * B, a.w) - qx0;
-    const int qh = min(fp.origin_y + (byq + 1) * B, a.h) - qy0;
-
-    const T* g = static_cast<const T*>(a.in.data) + (int64_t)(a.frame_base + f) * a.in.sn;
-    T* gi = static_cast<T*>(a.out.data) + (int64_t)(a.frame_base + f) * a.out.sn;
-
-    T* Ax = reinterpret_cast<T*>(smem);   // [px][qx]
-    T* Ay = Ax + B * B;                   // [py][qy]
-    T* gb = Ay + B * B;                   // [py][px]
-    T* tt = gb + B * B;                   // [py][qx]
-    double* wtab = reinterpret_cast<double*>(tt + B * B);
-    double* cdf = wtab + (2 * a.r_cap + 1);
-    double* red = cdf + (2 * a.r_cap + 1);
-
-    const int tid = threadIdx.x;
-    const int K = (a.r_cap + B - 1) / B;
-    const int nout = qw * qh;
-
-    for (int c = 0; c < a.c; ++c) {
-        T acc[kMaxOut];
+    const Frag F = describe(table, prefix, a.nframes, gid);
+    const FrameDesc& d = *F.fd;
+    const int r = radius[gid];
+    const T* __restrict__ w = wts + (size_t)gid * a.wstride;
+    const int xs = max(F.xa - r, 0), xe = min(F.xa + F.bw - 1 + r, d.w - 1);
+    const int G = (xe - xs + kPH) / kPH;
+    const T* g = static_cast<const T*>(d.in);
+    const int P = s.pitch_a;
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    for (int c0 = 0; c0 < d.c; c0 += s.chunk_c) {
+        const int cc = min(s.chunk_c, d.c - c0);
+        const int RT = cc * F.bh;
+        if (c0 > 0) __syncthreads();  // previous channels' rows are no longer read
+        for (int i = tid; i < RT * P; i += kThreads) {
+            const int row = i / P, col = i - row * P;
+            const int k = row / F.bh, py = row - k * F.bh;
+            const int x = col - kPadA;
+            T v = 0;
+            if (x >= 0 && x < F.bw)
+                v = g[(int64_t)(c0 + k) * d.isc + (int64_t)(F.ya + py) * d.ish + (int64_t)(F.xa + x) * d.isw];
+            rows[i] = v;
+        }
+        __syncthreads();
+        const int nchunk = (RT + 63) / 64;
+        for (int task = wave; task < nchunk * G; task += kThreads / 64) {
+            const int gi = task / nchunk, ch = task - gi * nchunk;
+            const int X = xs + gi * kPH;
+            // taps t with X + p + t inside the fragment for some p in 0..7
+            int t_lo = max(-r, F.xa - X - (kPH - 1));
+            const int t_hi = min(r, F.xa + F.bw - 1 - X);
+            const int row = ch * 64 + lane;
+            if (row >= RT) continue;
+            const T* rr = rows + row * P + kPadA - F.xa;  // rr[x]: this row's gradient at frame column x
+            T acc[kPH];
 #pragma unroll
-        for (int k = 0; k < kMaxOut; ++k) acc[k] = 0;
-        for (int by = max(byq - K, 0); by <= min(byq + K, nby - 1); ++by)
-            for (int bx = max(bxq - K, 0); bx <= min(bxq + K, nbx - 1); ++bx) {
-                const int lb = by * nbx + bx;
-                const double sigma = fp.sigma_map ? clip_map_sigma((double)fp.sigma_map[lb], fp.cap)
-                                                  : fragment_sigma_ramp(fp, bx, by);
-                int r = radius_of(sigma);
-                if (r > a.r_cap) r = a.r_cap;
-                const int px0 = max(fp.origin_x + bx * B, 0), py0 = max(fp.origin_y + by * B, 0);
-                const int bw = min(fp.origin_x + (bx + 1) * B, a.w) - px0;
-                const int bh = min(fp.origin_y + (by + 1) * B, a.h) - py0;
-                // reach along each axis (clamping keeps edge taps inside the frame)
-                if (px0 - r > qx0 + qw - 1 || px0 + bw - 1 + r < qx0) continue;
-                if (py0 - r > qy0 + qh - 1 || py0 + bh - 1 + r < qy0) continue;
-                const int N = 2 * r + 1;
-                // weights of fragment b, normalised, and their running sum
-                double part = 0.0;
-                const double inv = r > 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
-                for (int j = tid; j < N; j += kThreads) {
-                    const double k = (double)(j - r);
-                    const double v = r > 0 ? exp(-(k * k) * inv) : 1.0;
-                    wtab[j] = v;
-                    part += v;
+            for (int p = 0; p < kPH; ++p) acc[p] = 0;
+            if (t_lo <= t_hi) {
+                t_lo -= (X + t_lo - F.xa + kPadA) & (V - 1);  // aligned window start; taps below -r are zero
+                hconv(acc, rr + X + t_lo, t_hi - t_lo + 1, w + (t_lo + r));
+            }
+            if (xs == 0 && gi == 0) {  // column 0 collects the taps that fell off the left edge
+                T cdf = 0, corr = 0;
+                for (int m = -r; m <= -F.xa - 1; ++m) {
+                    cdf += w[m + r];
+                    const int x = -m - 1;
+                    if (x < F.xa + F.bw) corr = fma(cdf, rr[x], corr);
                 }
-                const double S = block_sum_d(part, red);  // syncs: wtab complete
-                for (int j = tid; j < N; j += kThreads) wtab[j] /= S;
-                __syncthreads();
-                if (tid == 0) {
-                    double s = 0.0;
-                    for (int j = 0; j < N; ++j) { s += wtab[j]; cdf[j] = s; }
+                acc[0] += corr;
+            }
+            const int jr = d.w - 1 - X;
+            if (xe == d.w - 1 && jr >= 0 && jr < kPH) {  // column w-1 collects those off the right edge
+                T cdf = 0, corr = 0;
+                for (int m = -r; m <= -1; ++m) {
+                    cdf += w[m + r];
+                    const int x = m + d.w;
+                    if (x >= F.xa && x < F.xa + F.bw) corr = fma(cdf, rr[x], corr);
                 }
-                __syncthreads();
-                for (int i = tid; i < bw * qw; i += kThreads) {
-                    const int p = i / qw, q = i - p * qw;
-                    Ax[p * B + q] = (T)folded(px0 + p, qx0 + q, r, a.w, wtab, cdf);
-                }
-                for (int i = tid; i < bh * qh; i += kThreads) {
-                    const int p = i / qh, q = i - p * qh;
-                    Ay[p * B + q] = (T)folded(py0 + p, qy0 + q, r, a.h, wtab, cdf);
-                }
-                for (int i = tid; i < bh * bw; i += kThreads) {
-                    const int y = i / bw, x = i - y * bw;
-                    gb[y * B + x] = g[c * a.in.sc + (int64_t)(py0 + y) * a.in.sh + (int64_t)(px0 + x) * a.in.sw];
-                }
-                __syncthreads();
-                // horizontal contraction: tt[py][qx] = sum_px gb[py][px] * Ax[px][qx]
-                for (int i = tid; i < bh * qw; i += kThreads) {
-                    const int y = i / qw, q = i - y * qw;
-                    T s = 0;
-                    for (int x = 0; x < bw; ++x) s = fma(gb[y * B + x], Ax[x * B + q], s);
-                    tt[y * B + q] = s;
-                }
-                __syncthreads();
-                // vertical contraction into this thread's outputs
 #pragma unroll
-                for (int k = 0; k < kMaxOut; ++k) {
-                    const int i = tid + k * kThreads;
-                    if (i < nout) {
-                        const int qy = i / qw, qx = i - qy * qw;
-                        T s = acc[k];
-                        for (int y = 0; y < bh; ++y) s = fma(Ay[y * B + qy], tt[y * B + qx], s);
-                        acc[k] = s;
+                for (int p = 0; p < kPH; ++p)
+                    if (p == jr) acc[p] += corr;
+            }
+            const int k = row / F.bh, py = row - k * F.bh;
+            T* dst = scratch + (((size_t)gid * s.cmax + (c0 + k)) * s.bmax + py) * s.sw + (X - F.xa + a.r_cap);
+#pragma unroll
+            for (int p = 0; p < kPH; ++p)
+                if (X + p <= xe) dst[p] = acc[p];
+        }
+    }
+}
+
+// Vertical gather into output tile gid: grad_in over the tile's rectangle.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, const AdjShape s,
+                                                             const FrameDesc* __restrict__ table,
+                                                             const int32_t* __restrict__ prefix,
+                                                             const int32_t* __restrict__ radius,
+                                                             const T* __restrict__ wts,
+                                                             const T* __restrict__ scratch) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* cols = reinterpret_cast<T*>(smem);  // [bmax columns][pitch_b rows]
+    constexpr int V = 16 / sizeof(T);
+    const int gid = blockIdx.x;
+    const Frag Q = describe(table, prefix, a.nframes, gid);
+    const FrameDesc& d = *Q.fd;
+    const FrameParams& fp = d.p;
+    const int nbx = fp.nbx, nby = d.nby;
+    const int first = gid - Q.lb;
+    const int K = (a.r_cap + fp.block - 1) / fp.block;  // fragments within reach on each side
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    const int PB = s.pitch_b, PAD = s.pad_b;
+    const int ngroups = (Q.bh + kPV - 1) / kPV;
+    const int ntask = s.bmax * ngroups;  // task i: column i % bmax, rows 4 (i / bmax) .. +3
+    const int by_lo = max(Q.by - K, 0), by_hi = min(Q.by + K, nby - 1);
+    const int bx_lo = max(Q.bx - K, 0), bx_hi = min(Q.bx + K, nbx - 1);
+    T* out = static_cast<T*>(d.out);
+    for (int c = 0; c < d.c; ++c) {
+        T acc[kAdjTasks][kPV];
+#pragma unroll
+        for (int k = 0; k < kAdjTasks; ++k)
+#pragma unroll
+            for (int p = 0; p < kPV; ++p) acc[k][p] = 0;
+        for (int by = by_lo; by <= by_hi; ++by)
+            for (int bx = bx_lo; bx <= bx_hi; ++bx) {
+                const int b = first + by * nbx + bx;
+                const Frag Fb = describe_at(Q.fd, first, b);
+                const int r = radius[b];
+                const int rx0 = max(Fb.xa - r, 0), rx1 = min(Fb.xa + Fb.bw - 1 + r, d.w - 1);
+                const int ry0 = max(Fb.ya - r, 0), ry1 = min(Fb.ya + Fb.bh - 1 + r, d.h - 1);
+                if (rx1 < Q.xa || rx0 >= Q.xa + Q.bw || ry1 < Q.ya || ry0 >= Q.ya + Q.bh) continue;
+                const T* __restrict__ w = wts + (size_t)b * a.wstride;
+                const T* src = scratch + ((size_t)b * s.cmax + c) * s.bmax * s.sw;
+                const int xoff = a.r_cap - Fb.xa;
+                __syncthreads();  // the previous fragment's columns are no longer read
+                // column x of the tile: PAD zero rows, b's rows, zeros to the pitch
+                const int nrg = PB / V;
+                for (int i = tid; i < Q.bw * nrg; i += kThreads) {
+                    const int rg = i / Q.bw, x = i - rg * Q.bw;
+                    const int gx = Q.xa + x;
+                    const bool inx = gx >= rx0 && gx <= rx1;
+                    T v[V];
+#pragma unroll
+                    for (int u = 0; u < V; ++u) {
+                        const int py = rg * V + u - PAD;
+                        v[u] = (inx && py >= 0 && py < Fb.bh) ? src[(size_t)py * s.sw + gx + xoff] : (T)0;
+                    }
+                    T* dst = cols + x * PB + rg * V;
+                    if constexpr (V == 4) {
+                        *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
+                        *reinterpret_cast<double2*>(dst) = make_double2(v[0], v[1]);
                     }
                 }
                 __syncthreads();
+#pragma unroll
+                for (int k = 0; k < kAdjTasks; ++k) {
+                    const int i0 = wave * 64 + k * kThreads;
+                    if (i0 >= ntask) break;
+                    // taps t with y + t inside fragment b for some row y of this wave
+                    const int gA = i0 / s.bmax, gB = min((i0 + 63) / s.bmax, ngroups - 1);
+                    const int ymin = Q.ya + kPV * gA, ymax = min(Q.ya + kPV * gB + kPV - 1, Q.ya + Q.bh - 1);
+                    int t_lo = max(-r, Fb.ya - ymax);
+                    const int t_hi = min(r, Fb.ya + Fb.bh - 1 - ymin);
+                    const int i = i0 + lane;
+                    const int x = i % s.bmax, gr = i / s.bmax;
+                    if (x >= Q.bw || gr >= ngroups) continue;
+                    const int y0 = Q.ya + kPV * gr;
+                    const T* col = cols + x * PB + PAD - Fb.ya;  // col[y]: b's transpose at frame row y
+                    if (t_lo <= t_hi) {
+                        t_lo -= (Q.ya + t_lo - Fb.ya + PAD) & (V - 1);  // aligned window start
+                        vconv(acc[k], col + y0 + t_lo, t_hi - t_lo + 1, w + (t_lo + r));
+                    }
+                    if (y0 == 0) {  // row 0 collects the taps that fell off the top edge
+                        T cdf = 0, corr = 0;
+                        for (int m = -r; m <= -Fb.ya - 1; ++m) {
+                            cdf += w[m + r];
+                            const int py = -m - 1;
+                            if (py < Fb.ya + Fb.bh) corr = fma(cdf, col[py], corr);
+                        }
+                        acc[k][0] += corr;
+                    }
+                    const int pr = d.h - 1 - y0;
+                    if (pr >= 0 && pr < kPV) {  // row h-1 collects those off the bottom edge
+                        T cdf = 0, corr = 0;
+                        for (int m = -r; m <= -1; ++m) {
+                            cdf += w[m + r];
+                            const int py = m + d.h;
+                            if (py >= Fb.ya && py < Fb.ya + Fb.bh) corr = fma(cdf, col[py], corr);
+                        }
+#pragma unroll
+                        for (int p = 0; p < kPV; ++p)
+                            if (p == pr) acc[k][p] += corr;
+                    }
+                }
             }
 #pragma unroll
-        for (int k = 0; k < kMaxOut; ++k) {
-            const int i = tid + k * kThreads;
-            if (i < nout) {
-                const int qy = i / qw, qx = i - qy * qw;
-                gi[c * a.out.sc + (int64_t)(qy0 + qy) * a.out.sh + (int64_t)(qx0 + qx) * a.out.sw] = acc[k];
+        for (int k = 0; k < kAdjTasks; ++k) {
+            const int i = wave * 64 + k * kThreads + lane;
+            if (i >= ntask) break;
+            const int x = i % s.bmax, gr = i / s.bmax;
+            if (x >= Q.bw || gr >= ngroups) continue;
+            T* o = out + c * d.osc + (int64_t)(Q.xa + x) * d.osw;
+#pragma unroll
+            for (int p = 0; p < kPV; ++p) {
+                const int y = Q.ya + kPV * gr + p;
+                if (y < Q.ya + Q.bh) o[(int64_t)y * d.osh] = acc[k][p];
             }
         }
     }
@@ -173,68 +254,73 @@ template <typename T>
 bool AdjSlot<T>::configured = false;
 
 template <typename T>
-fov_status launch_adj_typed(const AdjLaunch& a, int nblocks, size_t lds, hipStream_t stream, size_t lds_limit) {
-    auto kern = fov_adj_kernel<T>;
+fov_status launch_typed(const FwdLaunch& a, const AdjShape& s, const PlanBuffers& plan, void* scratch,
+                        hipStream_t stream, size_t lds_limit) {
+    auto kh = fov_adj_h_kernel<T>;
+    auto kv = fov_adj_v_kernel<T>;
+    hipError_t e;
     if (!AdjSlot<T>::configured) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
-        if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(adjoint)");
+        for (const void* k : {(const void*)kh, (const void*)kv}) {
+            hipFuncAttributes fa;
+            e = hipFuncGetAttributes(&fa, k);
+            if (e != hipSuccess) return hip_error(e, "hipFuncGetAttributes(adjoint)");
+            const size_t dyn_max = lds_limit > fa.sharedSizeBytes ? lds_limit - fa.sharedSizeBytes : 0;
+            e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max);
+            if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(adjoint)");
+        }
         AdjSlot<T>::configured = true;
     }
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreads), lds, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_error(e, "adjoint kernel launch");
+    const T* wts = static_cast<const T*>(plan.weights);
+    T* sc = static_cast<T*>(scratch);
+    hipLaunchKernelGGL(kh, dim3(a.nfrag), dim3(kThreads), adjoint_lds_h(s, sizeof(T)), stream, a, s,
+                       (const FrameDesc*)a.table, (const int32_t*)a.prefix, (const int32_t*)plan.radius, wts, sc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "adjoint horizontal kernel launch");
+    hipLaunchKernelGGL(kv, dim3(a.nfrag), dim3(kThreads), adjoint_lds_v(s, sizeof(T)), stream, a, s,
+                       (const FrameDesc*)a.table, (const int32_t*)a.prefix, (const int32_t*)plan.radius, wts,
+                       (const T*)sc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "adjoint vertical kernel launch");
     return FOV_OK;
 }
 
 }  // namespace
 
-size_t adjoint_lds_bytes(int r_cap, int B, int es) {
-    return (size_t)4 * B * B * es + (size_t)2 * (2 * r_cap + 1) * 8 + 64;
+AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax) {
+    AdjShape s;
+    s.bmax = bmax;
+    s.sw = bmax + 2 * r_cap;
+    s.cmax = cmax;
+    s.pitch_a = tile_pitch(bmax + kPadA + 7, es);
+    s.chunk_c = std::max(1, std::min(cmax, 128 / bmax));
+    // rows one wave's tasks span in the vertical kernel, minus one
+    const int span = std::min(kPV * (63 / bmax + 1) + kPV - 1, bmax - 1);
+    s.pad_b = round_up(span + 4, 4);
+    s.pitch_b = inter_pitch(bmax + 2 * s.pad_b, es);
+    return s;
 }
 
-fov_status launch_adjoint_all(const fov_tensor* go, const fov_tensor* gi, const fov_params* p, int32_t np,
-                              hipStream_t stream, size_t lds_limit) {
-    const int es = go->dtype == FOV_F64 ? 8 : 4;
-    for (int f0 = 0; f0 < go->n; f0 += kMaxFramesPerLaunch) {
-        const int nf = std::min(kMaxFramesPerLaunch, go->n - f0);
-        AdjLaunch a;
-        std::memset(&a, 0, sizeof(a));
-        a.in = View{go->data, go->sn, go->sc, go->sh, go->sw};
-        a.out = View{gi->data, gi->sn, gi->sc, gi->sh, gi->sw};
-        a.c = go->c; a.h = go->h; a.w = go->w;
-        a.nframes = nf;
-        a.frame_base = f0;
-        int r_cap = 0, bmax = 1, total = 0;
-        for (int i = 0; i < nf; ++i) {
-            const fov_params& pp = p[np == 1 ? 0 : f0 + i];
-            FrameParams& fr = a.fr[i];
-            fr.fix_x = pp.fix_x; fr.fix_y = pp.fix_y; fr.e0 = pp.e0; fr.slope = pp.slope; fr.cap = pp.cap;
-            fr.block = pp.block; fr.origin_x = pp.origin_x; fr.origin_y = pp.origin_y;
-            fr.nbx = grid_extent(go->w, pp.origin_x, pp.block);
-            fr.sigma_map = pp.sigma_map;
-            a.blk_prefix[i] = total;
-            const int nby = grid_extent(go->h, pp.origin_y, pp.block);
-            total += fr.nbx * nby;
-            int rm = 0;
-            if (pp.sigma_map) {
-                rm = radius_of(pp.cap);
-            } else {
-                const int xs[2] = {0, fr.nbx - 1}, ys[2] = {0, nby - 1};
-                for (int u = 0; u < 2; ++u)
-                    for (int v = 0; v < 2; ++v) rm = std::max(rm, radius_of(fragment_sigma_ramp(fr, xs[u], ys[v])));
-            }
-            r_cap = std::max(r_cap, rm);
-            bmax = std::max(bmax, pp.block);
-        }
-        a.blk_prefix[nf] = total;
-        a.r_cap = r_cap;
-        const size_t lds = adjoint_lds_bytes(r_cap, bmax, es);
-        if (lds > lds_limit) return set_error(FOV_ERANGE, "adjoint tile does not fit in LDS");
-        fov_status s = es == 8 ? launch_adj_typed<double>(a, total, lds, stream, lds_limit)
-                               : launch_adj_typed<float>(a, total, lds, stream, lds_limit);
-        if (s != FOV_OK) return s;
-    }
-    return FOV_OK;
+size_t adjoint_lds_h(const AdjShape& s, int es) { return (size_t)s.chunk_c * s.bmax * s.pitch_a * es; }
+
+size_t adjoint_lds_v(const AdjShape& s, int es) { return (size_t)s.bmax * s.pitch_b * es; }
+
+size_t adjoint_scratch_elems(const AdjShape& s, int nfrag) {
+    return (size_t)nfrag * s.cmax * s.bmax * s.sw;
+}
+
+fov_status launch_adjoint(const FwdLaunch& a, const AdjShape& s, int es, const PlanBuffers& plan, void* weights_base,
+                          void* scratch, hipStream_t stream, size_t lds_limit) {
+    if (a.nfrag <= 0) return FOV_OK;
+    if (adjoint_lds_h(s, es) + 64 > lds_limit || adjoint_lds_v(s, es) + 64 > lds_limit)
+        return set_error(FOV_ERANGE, "adjoint tiles do not fit in LDS");
+    hipLaunchKernelGGL(fov_adj_lead_kernel, dim3(1), dim3(64), 0, stream, static_cast<unsigned char*>(weights_base),
+                       kAdjWeightLead * es);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "adjoint lead kernel launch");
+    fov_status st = launch_plan_weights(a, es, plan, stream);
+    if (st != FOV_OK) return st;
+    return es == 8 ? launch_typed<double>(a, s, plan, scratch, stream, lds_limit)
+                   : launch_typed<float>(a, s, plan, scratch, stream, lds_limit);
 }
 
 }  // namespace fov

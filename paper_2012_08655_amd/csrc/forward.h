@@ -68,6 +68,11 @@ fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_
                           hipStream_t stream, size_t lds_limit, int cus, bool persist,
                           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
+// Plan kernel alone (radius, order key and normalised taps of every fragment,
+// float taps for wsize 4, double for 8); publishes the frame table when the
+// frames travel in the arguments.
+fov_status launch_plan_weights(const FwdLaunch& a, int wsize, const PlanBuffers& plan, hipStream_t stream);
+
 // Device plan for foveate_plan(): sigma and radius of every fragment.
 fov_status launch_plan(const FrameParams& fp, int nblk, double* sigma_out, int32_t* r_out, hipStream_t stream);
 

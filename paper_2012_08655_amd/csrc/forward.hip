@@ -28,16 +28,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include "conv.h"
+
 #include <algorithm>
 #include <cmath>
 
 namespace fov {
 
 namespace {
-
-constexpr int kPH = 8;  // outputs per thread, horizontal pass
-constexpr int kPV = 4;  // outputs per thread, vertical pass
-constexpr int kU = 4;   // taps per register-window step
 
 struct Geom {
     int N;   // taps, 2r+1
@@ -57,35 +55,6 @@ __host__ __device__ inline Geom geom(int r, int bw, int bh) {
     return g;
 }
 
-// Window loads run up to 3 elements past the last staged column and 4 rows
-// past the last intermediate row (values that no tap uses); the pitch and the
-// allocation leave room for them.
-constexpr int kColSlack = 4;
-constexpr int kRowSlack = 4;
-
-// Tile row pitch in elements.  A horizontal-pass lane reads 4 elements (4*es
-// bytes) per load from its own row, and the lanes of a group sit on
-// consecutive rows; rows start 4*es bytes apart modulo 128 so that 128/(4*es)
-// such lanes cover the 32 LDS banks once.
-__host__ __device__ inline int tile_pitch(int TW, int es) {
-    const int q = 4, m = 128 / es;
-    const int need = TW + kColSlack;
-    return round_up(need > q ? need - q : 1, m) + q;
-}
-
-// The intermediate is stored column-major (one column of TH rows after
-// another) so the vertical pass reads four rows with one 16-byte load.  Column
-// pitch in elements: columns start 16 bytes apart modulo 128 bytes (eight
-// lanes on eight consecutive columns hit 32 distinct banks), with room for
-// the window's overrun past the last row.
-__host__ __device__ inline int inter_pitch(int TH, int es) {
-    const int q = 16 / es, m = 128 / es;
-    const int need = TH + kRowSlack;
-    return round_up(need > q ? need - q : 1, m) + q;
-}
-
-__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
-
 // ---- element conversions ----------------------------------------------------------------------
 template <typename TS, typename TIn>
 __device__ __forceinline__ TS to_stage(TIn v) { return (TS)v; }
@@ -101,139 +70,6 @@ __device__ __forceinline__ uint8_t to_out<uint8_t, float>(float v) {
 
 template <typename TOut, typename TIn>
 __device__ __forceinline__ TOut copy_out(TIn v) { return (TOut)v; }
-
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-// Index of the calling wavefront in its workgroup, as a scalar (uniform) value.
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-// ---- LDS window loads -------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void load4_row(const T* p, T (&b)[4]) {
-    if constexpr (sizeof(T) == 2) {
-        // 8-byte load of four halves
-        const uint2 u = *reinterpret_cast<const uint2*>(p);
-        const _Float16* h = reinterpret_cast<const _Float16*>(&u);
-        b[0] = h[0]; b[1] = h[1]; b[2] = h[2]; b[3] = h[3];
-    } else if constexpr (sizeof(T) == 4) {
-        const float4 v = *reinterpret_cast<const float4*>(p);
-        b[0] = v.x; b[1] = v.y; b[2] = v.z; b[3] = v.w;
-    } else {
-        const double2 v0 = *reinterpret_cast<const double2*>(p);
-        const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
-        b[0] = v0.x; b[1] = v0.y; b[2] = v1.x; b[3] = v1.y;
-    }
-}
-
-template <int IP, typename T>
-__device__ __forceinline__ void load4_col(const T* p, T (&b)[4]) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) b[k] = p[k * IP];
-}
-
-// Horizontal step: taps j0..j0+NT-1 on 8 outputs; window = X ++ Y ++ Z[0..2].
-template <int NT = kU, typename TC, typename TS>
-__device__ __forceinline__ void hstep(TC (&acc)[kPH], const TS (&X)[4], const TS (&Y)[4], const TS (&Z)[4],
-                                      const TC* __restrict__ w) {
-#pragma unroll
-    for (int u = 0; u < NT; ++u) {
-        const TC wu = w[u];
-#pragma unroll
-        for (int p = 0; p < kPH; ++p) {
-            const int i = p + u;
-            const TS v = i < 4 ? X[i] : (i < 8 ? Y[i - 4] : Z[i - 8]);
-            acc[p] = fma(wu, (TC)v, acc[p]);
-        }
-    }
-}
-
-// Vertical step: taps j0..j0+NT-1 on 4 outputs; window = X ++ Y[0..2].
-template <int NT = kU, typename TC>
-__device__ __forceinline__ void vstep(TC (&acc)[kPV], const TC (&X)[4], const TC (&Y)[4], const TC* __restrict__ w) {
-#pragma unroll
-    for (int u = 0; u < NT; ++u) {
-        const TC wu = w[u];
-#pragma unroll
-        for (int p = 0; p < kPV; ++p) {
-            const int i = p + u;
-            acc[p] = fma(wu, i < 4 ? X[i] : Y[i - 4], acc[p]);
-        }
-    }
-}
-
-// Partial horizontal step of nt (1..3) taps.
-template <typename TC, typename TS>
-__device__ __forceinline__ void hstep_part(int nt, TC (&acc)[kPH], const TS (&X)[4], const TS (&Y)[4],
-                                           const TS (&Z)[4], const TC* __restrict__ w) {
-    if (nt == 1) hstep<1>(acc, X, Y, Z, w);
-    else if (nt == 2) hstep<2>(acc, X, Y, Z, w);
-    else hstep<3>(acc, X, Y, Z, w);
-}
-
-// 8 horizontal outputs from a staged row: N taps over inputs row[0 .. N+6].
-// Three 4-value buffers rotate through a 3-step unrolled loop, so no window
-// value is ever moved between registers.
-template <typename TC, typename TS>
-__device__ __forceinline__ void hconv(TC (&acc)[kPH], const TS* row, int N, const TC* __restrict__ w) {
-    TS A[4], B[4], C[4];
-    load4_row(row, A);
-    load4_row(row + 4, B);
-    int j0 = 0;
-    for (; j0 + 12 <= N; j0 += 12) {
-        load4_row(row + j0 + 8, C);
-        hstep(acc, A, B, C, w + j0);
-        load4_row(row + j0 + 12, A);
-        hstep(acc, B, C, A, w + j0 + 4);
-        load4_row(row + j0 + 16, B);
-        hstep(acc, C, A, B, w + j0 + 8);
-    }
-    int left = N - j0;  // 0..11, window state (A, B)
-    if (left == 0) return;
-    load4_row(row + j0 + 8, C);
-    if (left < 4) { hstep_part(left, acc, A, B, C, w + j0); return; }
-    hstep(acc, A, B, C, w + j0);
-    j0 += 4; left -= 4;  // state (B, C)
-    if (left == 0) return;
-    load4_row(row + j0 + 8, A);
-    if (left < 4) { hstep_part(left, acc, B, C, A, w + j0); return; }
-    hstep(acc, B, C, A, w + j0);
-    j0 += 4; left -= 4;  // state (C, A), left 0..3
-    if (left == 0) return;
-    load4_row(row + j0 + 8, B);
-    hstep_part(left, acc, C, A, B, w + j0);
-}
-
-template <typename TC>
-__device__ __forceinline__ void vstep_part(int nt, TC (&acc)[kPV], const TC (&X)[4], const TC (&Y)[4],
-                                           const TC* __restrict__ w) {
-    if (nt == 1) vstep<1>(acc, X, Y, w);
-    else if (nt == 2) vstep<2>(acc, X, Y, w);
-    else vstep<3>(acc, X, Y, w);
-}
-
-// 4 vertical outputs from a column of the (column-major) intermediate: N
-// taps over col[0 .. N+2]; two buffers alternate through a 2-step loop.
-template <typename TC>
-__device__ __forceinline__ void vconv(TC (&acc)[kPV], const TC* col, int N, const TC* __restrict__ w) {
-    TC A[4], B[4];
-    load4_row(col, A);
-    int j0 = 0;
-    for (; j0 + 8 <= N; j0 += 8) {
-        load4_row(col + j0 + 4, B);
-        vstep(acc, A, B, w + j0);
-        load4_row(col + j0 + 8, A);
-        vstep(acc, B, A, w + j0 + 4);
-    }
-    int left = N - j0;  // 0..7, state A
-    if (left == 0) return;
-    load4_row(col + j0 + 4, B);
-    if (left < 4) { vstep_part(left, acc, A, B, w + j0); return; }
-    vstep(acc, A, B, w + j0);
-    j0 += 4; left -= 4;  // state B
-    if (left == 0) return;
-    load4_row(col + j0 + 4, A);
-    vstep_part(left, acc, B, A, w + j0);
-}
 
 // ---- staging of the padded tile ---------------------------------------------------------------
 // The tile is staged into LDS in strips of at most kStripMax rows.  Each strip
@@ -362,47 +198,6 @@ struct Stager<uint8_t, _Float16> {
         }
     }
 };
-
-// ---- fragments of a launch ---------------------------------------------------------------------
-// Last frame whose first fragment is <= gid (prefix has nframes+1 entries).
-__device__ __forceinline__ int frame_search(const int32_t* __restrict__ prefix, int nframes, int gid) {
-    int lo = 0, hi = nframes - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= gid) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Everything the kernels need to know about one fragment.
-struct Frag {
-    const FrameDesc* fd;
-    int lb, bx, by, xa, ya, bw, bh;
-};
-
-__device__ __forceinline__ Frag describe_at(const FrameDesc* fd, int first, int gid) {
-    Frag F;
-    F.fd = fd;
-    const FrameParams& fp = fd->p;
-    F.lb = gid - first;
-    F.by = F.lb / fp.nbx;
-    F.bx = F.lb - F.by * fp.nbx;
-    const int B = fp.block;
-    const int X0 = fp.origin_x + F.bx * B, Y0 = fp.origin_y + F.by * B;
-    F.xa = max(X0, 0);
-    F.ya = max(Y0, 0);
-    F.bw = min(X0 + B, fd->w) - F.xa;
-    F.bh = min(Y0 + B, fd->h) - F.ya;
-    return F;
-}
-
-// Fragment gid, reading frames from the device table (main kernel).
-__device__ __forceinline__ Frag describe(const FrameDesc* __restrict__ table, const int32_t* __restrict__ prefix,
-                                         int nframes, int gid) {
-    const int f = frame_search(prefix, nframes, gid);
-    return describe_at(table + f, prefix[f], gid);
-}
 
 // Narrow a fragment to output tile `sub` of its L-level split: tiles of
 // T = ceil(B / 2^L) pixels a side, row-major, clipped to the fragment and the
@@ -844,6 +639,20 @@ fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_
     if (in_dtype == FOV_F64 && out_dtype == FOV_F64)
         return launch_typed<double, double, double, double>(a, lds, plan, stream, lds_limit, cus, persist, ev_start, ev_stop);
     return set_error(FOV_EDTYPE, "unsupported dtype pair");
+}
+
+fov_status launch_plan_weights(const FwdLaunch& a, int wsize, const PlanBuffers& plan, hipStream_t stream) {
+    if (a.nfrag <= 0) return FOV_OK;
+    const int nrings = order_rings(a.r_cap), nang = order_angle_bins(nrings);
+    if (wsize == 8)
+        hipLaunchKernelGGL(fov_plan_weights_kernel<double>, dim3(a.nfrag), dim3(64), 0, stream, a, plan.radius,
+                           plan.okey, nrings, nang, static_cast<double*>(plan.weights));
+    else
+        hipLaunchKernelGGL(fov_plan_weights_kernel<float>, dim3(a.nfrag), dim3(64), 0, stream, a, plan.radius,
+                           plan.okey, nrings, nang, static_cast<float*>(plan.weights));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "plan kernel launch");
+    return FOV_OK;
 }
 
 fov_status launch_plan(const FrameParams& fp, int nblk, double* sigma_out, int32_t* r_out, hipStream_t stream) {
