@@ -267,7 +267,10 @@ fov_status foveate_server_create(const fov_server_cfg* cfg, fov_server** out);
  * dtype pair; p its parameters (block <= max_block, every fragment's sigma
  * <= max_sigma, at most max_fragments fragments).  The buffers (and a sigma
  * map, if any) must stay alive until poll reports the ticket done.  Returns
- * immediately with *ticket.  FOV_EAGAIN: request table full (poll and retry);
+ * with *ticket without waiting for the GPU; when a stream is free and no frame
+ * is queued, the frame's batch is launched from the calling thread before
+ * returning (the server's device is made current for that and restored).
+ * FOV_EAGAIN: request table full (poll and retry);
  * FOV_ECLOSED: the server is being destroyed; FOV_EINVAL / FOV_ERANGE /
  * FOV_EDTYPE / FOV_EALIAS as for forward, or a frame larger than the budget.
  */

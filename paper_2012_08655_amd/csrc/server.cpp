@@ -8,7 +8,9 @@
 // batch limits) as one batched forward on a free stream; a host function
 // queued after each batch marks its frames done and frees the stream, which
 // wakes the scheduler.  Frames that arrive while batches run are admitted and
-// launched on another stream, so batches overlap on the device.
+// launched on another stream, so batches overlap on the device.  A frame that
+// arrives with a stream free and nothing queued is launched by the submitting
+// thread itself, which saves the hand-off to the scheduler.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -240,61 +242,66 @@ fov_status launch_batch(ServerImpl* s, Slot& sl, const std::vector<FrameDesc>& f
     return FOV_OK;
 }
 
+// Admit what the budget allows (FIFO) and, if a stream is free, launch
+// everything admitted (up to the batch limits) on it.  Called and returns with
+// lk held; the lock is released around the launch itself.  True if a batch
+// was launched.
+bool dispatch_once(ServerImpl* s, std::unique_lock<std::mutex>& lk) {
+    while (!s->pending.empty()) {
+        Req& r = s->reqs[s->pending.front()];
+        if (s->inflight_bytes + r.bytes > s->cfg.hbm_budget_bytes) break;
+        s->inflight_bytes += r.bytes;
+        r.t.t_admit = now_s();
+        s->admitted.push_back(s->pending.front());
+        s->pending.pop_front();
+    }
+    Slot* free_slot = nullptr;
+    for (Slot& sl : s->slots)
+        if (!sl.busy) {
+            free_slot = &sl;
+            break;
+        }
+    if (!free_slot || s->admitted.empty()) return false;
+    std::vector<uint64_t> ids;
+    std::vector<FrameDesc> frames;
+    int nfrag = 0;
+    size_t bytes = 0;
+    while (!s->admitted.empty() && (int)ids.size() < s->cfg.max_batch_frames) {
+        Req& r = s->reqs[s->admitted.front()];
+        if (!ids.empty() && nfrag + r.nfrag > s->cfg.max_fragments) break;
+        ids.push_back(s->admitted.front());
+        frames.push_back(make_frame_desc(r.in, r.out, 0, r.p));
+        nfrag += r.nfrag;
+        bytes += r.bytes;
+        s->admitted.pop_front();
+    }
+    const double t = now_s();
+    for (uint64_t id : ids) {
+        Req& r = s->reqs[id];
+        r.t.t_launch = t;
+        r.t.batch_frames = (int32_t)ids.size();
+    }
+    ++s->batches;
+    free_slot->busy = true;
+    free_slot->tickets = ids;
+    free_slot->bytes = bytes;
+    free_slot->status =
+        (s->cfg.test_fail_every > 0 && s->batches % (uint64_t)s->cfg.test_fail_every == 0) ? FOV_EHIP : FOV_OK;
+    lk.unlock();
+    const fov_status st = launch_batch(s, *free_slot, frames, nfrag);
+    if (st != FOV_OK) {
+        free_slot->status = st;
+        on_batch_done(free_slot);
+    }
+    lk.lock();
+    return true;
+}
+
 void scheduler_loop(ServerImpl* s) {
     if (!s->fake_mode()) (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // admission, FIFO, by HBM budget
-        while (!s->pending.empty()) {
-            Req& r = s->reqs[s->pending.front()];
-            if (s->inflight_bytes + r.bytes > s->cfg.hbm_budget_bytes) break;
-            s->inflight_bytes += r.bytes;
-            r.t.t_admit = now_s();
-            s->admitted.push_back(s->pending.front());
-            s->pending.pop_front();
-        }
-        Slot* free_slot = nullptr;
-        for (Slot& sl : s->slots)
-            if (!sl.busy) {
-                free_slot = &sl;
-                break;
-            }
-        if (free_slot && !s->admitted.empty()) {
-            // everything admitted, up to the batch limits, in arrival order
-            std::vector<uint64_t> ids;
-            std::vector<FrameDesc> frames;
-            int nfrag = 0;
-            size_t bytes = 0;
-            while (!s->admitted.empty() && (int)ids.size() < s->cfg.max_batch_frames) {
-                Req& r = s->reqs[s->admitted.front()];
-                if (!ids.empty() && nfrag + r.nfrag > s->cfg.max_fragments) break;
-                ids.push_back(s->admitted.front());
-                frames.push_back(make_frame_desc(r.in, r.out, 0, r.p));
-                nfrag += r.nfrag;
-                bytes += r.bytes;
-                s->admitted.pop_front();
-            }
-            const double t = now_s();
-            for (uint64_t id : ids) {
-                Req& r = s->reqs[id];
-                r.t.t_launch = t;
-                r.t.batch_frames = (int32_t)ids.size();
-            }
-            ++s->batches;
-            free_slot->busy = true;
-            free_slot->tickets = ids;
-            free_slot->bytes = bytes;
-            free_slot->status =
-                (s->cfg.test_fail_every > 0 && s->batches % (uint64_t)s->cfg.test_fail_every == 0) ? FOV_EHIP : FOV_OK;
-            lk.unlock();
-            const fov_status st = launch_batch(s, *free_slot, frames, nfrag);
-            if (st != FOV_OK) {
-                free_slot->status = st;
-                on_batch_done(free_slot);
-            }
-            lk.lock();
-            continue;
-        }
+        if (dispatch_once(s, lk)) continue;
         if (s->closing && s->pending.empty() && s->admitted.empty() && s->busy_slots() == 0) break;
         s->cv.wait(lk);
     }
@@ -411,7 +418,7 @@ fov_status foveate_submit(fov_server* srv, const fov_tensor* in, const fov_tenso
         r.bytes = view_bytes(*in) + view_bytes(*out);
         if (r.bytes > s->cfg.hbm_budget_bytes) return set_error(FOV_EINVAL, "frame larger than the HBM budget");
     }
-    std::lock_guard<std::mutex> lk(s->mu);
+    std::unique_lock<std::mutex> lk(s->mu);
     if (s->closing) return set_error(FOV_ECLOSED, "server is shutting down");
     if ((int64_t)s->reqs.size() >= s->cfg.max_requests) return set_error(FOV_EAGAIN, "request table full");
     const uint64_t id = s->next_ticket++;
@@ -421,9 +428,19 @@ fov_status foveate_submit(fov_server* srv, const fov_tensor* in, const fov_tenso
         r.t.t_admit = r.t.t_launch = r.t.t_done = r.t.t_submit;
     }
     s->reqs.emplace(id, r);
-    if (!empty) s->pending.push_back(id);
-    s->cv.notify_all();
     *ticket = id;
+    if (empty) return FOV_OK;
+    s->pending.push_back(id);
+    // Fast path: with a stream free and nothing queued ahead, the calling
+    // thread admits and launches right away (no hand-off to the scheduler);
+    // otherwise the scheduler batches the frame with whatever else waits.
+    if (s->pending.size() == 1 && s->admitted.empty()) {
+        int prev = -1;
+        if (!s->fake_mode() && hipGetDevice(&prev) == hipSuccess && prev != s->device) (void)hipSetDevice(s->device);
+        (void)dispatch_once(s, lk);
+        if (prev >= 0 && prev != s->device) (void)hipSetDevice(prev);
+    }
+    s->cv.notify_all();
     return FOV_OK;
 }
 
