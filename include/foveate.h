@@ -97,6 +97,19 @@ typedef struct {
 fov_status foveate_grid(int32_t h, int32_t w, const fov_params* p, int32_t* nbx, int32_t* nby);
 
 /*
+ * Fragment shift (Alg. 1; Sec. 3 on the SSIM map): the tiling origin that
+ * centres one fragment on the fixation, so that the copied fovea is as small
+ * as possible and the blur moves with the gaze instead of snapping into place
+ * at fragment boundaries.  Along each axis the fragment [s, s + B) with s the
+ * integer nearest to fix - (B - 1)/2 (halves round up) has its midpoint within
+ * half a pixel of the fixation; *origin_x / *origin_y receive s reduced into
+ * (-B, 0].  block in 1..64 and a finite fixation, else FOV_EINVAL.  Host-only
+ * arithmetic; copy the results into fov_params.origin_x / origin_y.
+ */
+fov_status foveate_fragment_shift(double fix_x, double fix_y, int32_t block, int32_t* origin_x,
+                                  int32_t* origin_y);
+
+/*
  * Per-fragment plan (Alg. 1 "grid of blurring strengths"), computed ON THE
  * DEVICE by the same code the kernels run: sigma_out[by*nbx+bx] (double) and
  * r_out[...] (int32), both device arrays of nby*nbx entries owned by the

@@ -4,4 +4,4 @@ Imported by the test suite, the smoke check and the benchmark's CPU-baseline
 leg; never by the product library.
 """
 from .oracle import (adjoint, build, eq7_shared_bytes, explicit_matrix, forward,  # noqa: F401
-                     forward_points, grid, max_filter_taps, max_threads, plan, to_u8)
+                     forward_points, fragment_shift, grid, max_filter_taps, max_threads, plan, to_u8)

@@ -13,6 +13,8 @@ adds two NumPy helpers that are themselves definitions:
   applying it to unit impulses (tiny frames only), so its transpose can be
   compared with :func:`adjoint`.
 * :func:`to_u8` -- the 8-bit output rule: round half to even, clip to 0..255.
+* :func:`fragment_shift` -- the tiling origin that centres one fragment on
+  the fixation (Alg. 1, Sec. 3 "SSIM"), in plain Python.
 
 Arrays are [c, h, w] (or [n, c, h, w]) float64; frame parameters are plain
 dicts with keys fix_x, fix_y, e0, slope, cap, block, origin_x, origin_y.
@@ -110,6 +112,27 @@ def grid(h: int, w: int, p: Mapping) -> tuple[int, int]:
     f = _frame(p)
     _load().orc_grid(h, w, ctypes.byref(f), ctypes.byref(nbx), ctypes.byref(nby))
     return nby.value, nbx.value
+
+
+def fragment_shift(p: Mapping) -> dict:
+    """Parameters with the tiling origin moved so that one fragment is centred
+    on the fixation (Alg. 1: the fragment shift; Sec. 3: centring a single
+    fragment on the fixation keeps the untouched fovea small and lets the blur
+    follow the gaze instead of snapping at fragment boundaries).
+
+    Along each axis the fragment [s, s + B) has its midpoint s + (B - 1)/2
+    (pixel-centre coordinates) nearest the fixation f when s is the integer
+    nearest to f - (B - 1)/2 (halves round up).  The origin is s reduced into
+    (-B, 0], the range the tiling origin takes.
+    """
+    B = int(p.get("block", 32))
+    out = dict(p)
+    for axis in ("x", "y"):
+        f = float(p["fix_" + axis])
+        start = int(np.floor(f - (B - 1) / 2.0 + 0.5))
+        o = start % B  # Python's modulo: 0 .. B-1
+        out["origin_" + axis] = o - B if o > 0 else 0
+    return out
 
 
 def plan(h: int, w: int, p: Mapping, sigma_map=None) -> tuple[np.ndarray, np.ndarray]:

@@ -213,6 +213,17 @@ def grid(h: int, w: int, params: Mapping) -> tuple[int, int]:
     return nby.value, nbx.value
 
 
+def fragment_shift(params: Mapping) -> dict:
+    """Copy of ``params`` with the tiling origin that centres one fragment on
+    the fixation (foveate_fragment_shift)."""
+    ox, oy = ctypes.c_int32(), ctypes.c_int32()
+    N.check(N.lib().foveate_fragment_shift(float(params["fix_x"]), float(params["fix_y"]),
+                                           int(params.get("block", 32)), ctypes.byref(ox), ctypes.byref(oy)))
+    out = dict(params)
+    out["origin_x"], out["origin_y"] = ox.value, oy.value
+    return out
+
+
 def plan_device(h: int, w: int, params: Mapping, device="cuda"):
     """Per-fragment (sigma f64, radius i32) computed by the device planner."""
     nby, nbx = grid(h, w, params)

@@ -286,6 +286,11 @@ fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params
     *empty = is_empty(*in);
     if (*empty) return FOV_OK;
     if ((s = check_alias(*in, *out)) != FOV_OK) return s;
+    if (in->dtype == FOV_U8) {
+        // 8-bit frames are read through 32-bit buffer offsets
+        const int64_t span = (int64_t)(in->c - 1) * in->sc + (int64_t)(in->h - 1) * in->sh + (int64_t)(in->w - 1) * in->sw + 1;
+        if (span >= ((int64_t)1 << 31)) return set_error(FOV_EINVAL, "an 8-bit frame may span at most 2^31 - 1 bytes");
+    }
     if (!p) return set_error(FOV_EINVAL, "params is NULL");
     if (np != in->n && np != 1) return set_error(FOV_EINVAL, "np must equal n or 1");
     for (int i = 0; i < np; ++i)
@@ -583,6 +588,22 @@ fov_status foveate_grid(int32_t h, int32_t w, const fov_params* p, int32_t* nbx,
     if (s != FOV_OK) return s;
     *nbx = grid_extent(w, p->origin_x, p->block);
     *nby = grid_extent(h, p->origin_y, p->block);
+    return FOV_OK;
+}
+
+fov_status foveate_fragment_shift(double fix_x, double fix_y, int32_t block, int32_t* origin_x,
+                                  int32_t* origin_y) {
+    if (!origin_x || !origin_y) return set_error(FOV_EINVAL, "NULL argument");
+    if (block < 1 || block > kMaxBlock) return set_error(FOV_EINVAL, "block must be in 1..64");
+    if (!std::isfinite(fix_x) || !std::isfinite(fix_y) || std::fabs(fix_x) > 1e9 || std::fabs(fix_y) > 1e9)
+        return set_error(FOV_EINVAL, "fixation must be finite (|f| <= 1e9)");
+    auto origin = [block](double f) {
+        const int64_t s = (int64_t)std::floor(f - 0.5 * (block - 1) + 0.5);  // start of the centred fragment
+        const int64_t m = ((s % block) + block) % block;
+        return (int32_t)(m == 0 ? 0 : m - block);
+    };
+    *origin_x = origin(fix_x);
+    *origin_y = origin(fix_y);
     return FOV_OK;
 }
 

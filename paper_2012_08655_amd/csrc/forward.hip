@@ -92,7 +92,8 @@ struct Stager {
     int64_t ish, isw;
     int y0, rows, h, w, x_first, TW;
 
-    __device__ __forceinline__ void setup(int x_first_, int TW_, int w_, int64_t isw_, int64_t ish_, int h_) {
+    __device__ __forceinline__ void setup(int x_first_, int TW_, int w_, int64_t isw_, int64_t ish_, int h_,
+                                          const TIn*, uint32_t) {
         x_first = x_first_; TW = TW_; w = w_; isw = isw_; ish = ish_; h = h_;
         const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -140,7 +141,11 @@ struct Stager {
 // 8-bit input staged as exact fp16, two columns per lane and one 32-bit LDS
 // write per pair: the bytes b0, b1 are placed under the fp16 exponent of 1024
 // (bits 0x6400 | b encode 1024 + b exactly) and 1024 is subtracted from both
-// halves at once.  One 128-column chunk is prefetched.
+// halves at once.  One 128-column chunk is prefetched.  Bytes are read with
+// buffer loads over the frame (a descriptor covering its bytes): each lane's
+// two column offsets are fixed for the fragment and a row's offset is a
+// wave-uniform scalar, so no per-row address arithmetic runs on the vector
+// unit; reads past the descriptor's range would return 0.
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ half2_t bytes_to_half2(uint32_t b0, uint32_t b1) {
@@ -149,32 +154,46 @@ __device__ __forceinline__ half2_t bytes_to_half2(uint32_t b0, uint32_t b1) {
     return __builtin_bit_cast(half2_t, bits) - bias;
 }
 
+// Raw buffer descriptor (dword 3 as gfx9 expects for untyped access).
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ uint32_t load_byte(__amdgpu_buffer_rsrc_t rsrc, uint32_t voff, uint32_t soff) {
+    return (uint32_t)(uint8_t)__builtin_amdgcn_raw_buffer_load_b8(rsrc, (int)voff, (int)soff, 0);
+}
+
 template <>
 struct Stager<uint8_t, _Float16> {
     uint32_t b0[kRowsPerWave], b1[kRowsPerWave];
     uint32_t c0, c1;
     bool cv;
-    const uint8_t* plane;
-    int64_t ish, isw;
+    __amdgpu_buffer_rsrc_t rsrc;
+    const uint8_t* base;
+    uint32_t poff, ish;
+    uint32_t isw;
     int y0, rows, h, w, x_first, TW;
 
-    __device__ __forceinline__ void setup(int x_first_, int TW_, int w_, int64_t isw_, int64_t ish_, int h_) {
-        x_first = x_first_; TW = TW_; w = w_; isw = isw_; ish = ish_; h = h_;
+    // base: the frame's first byte; span: bytes from base to its last byte + 1 (< 2^31)
+    __device__ __forceinline__ void setup(int x_first_, int TW_, int w_, int64_t isw_, int64_t ish_, int h_,
+                                          const uint8_t* base_, uint32_t span) {
+        x_first = x_first_; TW = TW_; w = w_; isw = (uint32_t)isw_; ish = (uint32_t)ish_; h = h_;
+        base = base_;
+        rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base_), 0, (int)span, kBufferWord3);
         const int tx = 2 * (threadIdx.x & 63);  // tx + 1 < TP always
         cv = tx < TW;
-        c0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * (uint32_t)isw;
-        c1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * (uint32_t)isw;
+        c0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * isw;
+        c1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * isw;
     }
     __device__ __forceinline__ void issue(const uint8_t* plane_, int y0_, int rows_) {
-        plane = plane_; y0 = y0_; rows = rows_;
+        poff = (uint32_t)(plane_ - base);
+        y0 = y0_; rows = rows_;
         const int wave = wave_id();
 #pragma unroll
         for (int rb = 0; rb < kRowsPerWave; ++rb) {
             const int ty = wave + rb * (kThreads / 64);
             if (ty < rows && cv) {
-                const uint8_t* rp = plane + (int64_t)clampi(y0 + ty, 0, h - 1) * ish;
-                b0[rb] = rp[c0];
-                b1[rb] = rp[c1];
+                const uint32_t soff = poff + (uint32_t)clampi(y0 + ty, 0, h - 1) * ish;
+                b0[rb] = load_byte(rsrc, c0, soff);
+                b1[rb] = load_byte(rsrc, c1, soff);
             }
         }
     }
@@ -189,16 +208,18 @@ struct Stager<uint8_t, _Float16> {
         for (int k0 = 128; k0 < TW; k0 += 128) {
             const int tx = k0 + 2 * lane;
             if (tx >= TW) continue;
-            const uint32_t d0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * (uint32_t)isw;
-            const uint32_t d1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * (uint32_t)isw;
+            const uint32_t d0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * isw;
+            const uint32_t d1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * isw;
             for (int ty = wave; ty < rows; ty += kThreads / 64) {
-                const uint8_t* rp = plane + (int64_t)clampi(y0 + ty, 0, h - 1) * ish;
-                *reinterpret_cast<half2_t*>(tile + ty * TP + tx) = bytes_to_half2(rp[d0], rp[d1]);
+                const uint32_t soff = poff + (uint32_t)clampi(y0 + ty, 0, h - 1) * ish;
+                *reinterpret_cast<half2_t*>(tile + ty * TP + tx) =
+                    bytes_to_half2(load_byte(rsrc, d0, soff), load_byte(rsrc, d1, soff));
             }
         }
     }
 };
 
+// ---- fragments of a launch ---------------------------------------------------------------------
 // Narrow a fragment to output tile `sub` of its L-level split: tiles of
 // T = ceil(B / 2^L) pixels a side, row-major, clipped to the fragment and the
 // frame.  Returns false for a tile that holds no pixel (ragged splits).
@@ -257,7 +278,8 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
     const int nst = (g.TH + SR - 1) / SR;
     const int nunits = d.c * nst;
     Stager<TIn, TS> st;
-    st.setup(F.xa - r, g.TW, d.w, d.isw, d.ish, d.h);
+    const int64_t span = (int64_t)(d.c - 1) * d.isc + (int64_t)(d.h - 1) * d.ish + (int64_t)(d.w - 1) * d.isw + 1;
+    st.setup(F.xa - r, g.TW, d.w, d.isw, d.ish, d.h, in, (uint32_t)span);
     st.issue(in, F.ya - r, SR);
     st.commit(tile, TP);
     __syncthreads();

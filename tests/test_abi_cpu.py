@@ -174,3 +174,29 @@ def test_tuning_file_roundtrip_and_errors(tmp_path):
     assert lib.foveate_tuning_load(str(tmp_path / "missing.txt").encode()) == N.FOV_EINVAL
     assert lib.foveate_tuning_clear() == N.FOV_OK
     assert lib.foveate_tuning_count(ctypes.byref(n)) == N.FOV_OK and n.value == 0
+
+
+def test_u8_frame_span_limit():
+    # 8-bit frames are addressed with 32-bit offsets: a frame spanning 2^31 bytes is refused
+    a = fake_desc(N.FOV_U8, 1, 1, 2, 64, 0x10000000)
+    a.sh = 1 << 31
+    b = fake_desc(N.FOV_U8, 1, 1, 2, 64, 0x10000000 + (1 << 33))
+    assert call_fwd(a, b, P0) == N.FOV_EINVAL
+    assert "2^31" in N.lib().foveate_last_error().decode()
+
+
+def test_fragment_shift_matches_oracle(orc):
+    L = N.lib()
+    rng = np.random.default_rng(21)
+    ox, oy = ctypes.c_int32(), ctypes.c_int32()
+    for i in range(2000):
+        B = int(rng.integers(1, 65))
+        fx, fy = rng.uniform(-100, 5000, size=2)
+        if i % 3 == 0:
+            fx, fy = np.round(fx * 2) / 2, np.round(fy * 2) / 2  # exact halves
+        assert L.foveate_fragment_shift(fx, fy, B, ctypes.byref(ox), ctypes.byref(oy)) == N.FOV_OK
+        ref = orc.fragment_shift(synth.params_dict(fx, fy, 0, 0.1, 4, B))
+        assert (ox.value, oy.value) == (ref["origin_x"], ref["origin_y"]), (fx, fy, B)
+    assert L.foveate_fragment_shift(1.0, 1.0, 0, ctypes.byref(ox), ctypes.byref(oy)) == N.FOV_EINVAL
+    assert L.foveate_fragment_shift(float("nan"), 1.0, 32, ctypes.byref(ox), ctypes.byref(oy)) == N.FOV_EINVAL
+    assert L.foveate_fragment_shift(1.0, 1.0, 32, None, ctypes.byref(oy)) == N.FOV_EINVAL

@@ -231,3 +231,64 @@ def test_adjoint_dot_identity(orc):
 def test_to_u8_rounds_half_even(orc):
     v = np.array([-3.0, 0.5, 1.5, 2.5, 254.5, 255.49, 300.0])
     assert orc.to_u8(v).tolist() == [0, 0, 2, 2, 254, 255, 255]
+
+
+# ---- fragment shift (Alg. 1; Sec. 3) ------------------------------------------------------------
+
+def _golden_rows(name):
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+def test_fragment_shift_hand_worked(orc):
+    rows = _golden_rows("fragment_shift_worked.txt")
+    assert len(rows) == 7
+    for fx, fy, B, ox, oy in rows:
+        p = orc.fragment_shift(synth.params_dict(float(fx), float(fy), 0, 0.1, 4, int(B)))
+        assert (p["origin_x"], p["origin_y"]) == (int(ox), int(oy)), (fx, fy, B)
+
+
+def test_fragment_shift_centres_a_fragment(orc):
+    # brute force over fragments: some midpoint lies within half a pixel of the fixation,
+    # and the origin is in (-B, 0]
+    rng = np.random.default_rng(12)
+    for _ in range(400):
+        B = int(rng.integers(1, 65))
+        fx, fy = rng.uniform(-50, 3000, size=2)
+        if rng.random() < 0.3:  # exact halves
+            fx, fy = np.round(fx * 2) / 2, np.round(fy * 2) / 2
+        p = orc.fragment_shift(synth.params_dict(fx, fy, 0, 0.1, 4, B))
+        for f, o in ((fx, p["origin_x"]), (fy, p["origin_y"])):
+            assert -B < o <= 0
+            mids = o + np.arange(-4, 3100 // B + 4) * B + (B - 1) / 2.0
+            assert np.min(np.abs(mids - f)) <= 0.5 + 1e-12
+
+
+def _translate_cols(x, k):
+    """x shifted right by k columns (the first k columns repeat column 0)."""
+    y = np.empty_like(x)
+    y[..., k:] = x[..., :-k]
+    y[..., :k] = x[..., :1]
+    return y
+
+
+def test_fragment_shift_makes_blur_follow_the_gaze(orc):
+    # Translating frame and fixation by k pixels translates the output (away from the borders)
+    # when the tiling follows the fixation; with a fixed tiling the fragments stay put and the
+    # blur does not follow (Sec. 3: it would snap at fragment boundaries).
+    rng = np.random.default_rng(13)
+    x = rng.random((1, 80, 120))
+    B, k = 16, 5
+    base = synth.params_dict(50.25, 40.25, 4.0, 0.1, 2.0, B)  # r <= 6; quarter-pixel fixation
+    r = 6
+    shifted = dict(base, fix_x=base["fix_x"] + k)
+    y0 = orc.forward(x, orc.fragment_shift(base))
+    y1 = orc.forward(_translate_cols(x, k), orc.fragment_shift(shifted))
+    assert np.max(np.abs(y1[..., r + k:120 - r] - y0[..., r:120 - k - r])) <= 1e-12
+    z0 = orc.forward(x, base)
+    z1 = orc.forward(_translate_cols(x, k), shifted)
+    assert np.max(np.abs(z1[..., r + k:120 - r] - z0[..., r:120 - k - r])) > 1e-3
