@@ -107,3 +107,16 @@ def test_cfg5_training_batches(fov, orc, dev):
         i = n // 2
         ref = orc.adjoint(g[i].cpu().numpy().astype(np.float64), plist[i])
         assert np.max(np.abs(gx[i] - ref)) <= 2e-5 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("B", [64, 24])
+def test_adjoint_largest_and_odd_blocks_f64(fov, orc, dev, B):
+    # 64 px fragments use four output tasks per thread in the vertical gather
+    rng = np.random.default_rng(300 + B)
+    h, w, c = 150, 170, 2
+    p = synth.params_dict(rng.uniform(0, w - 1), rng.uniform(0, h - 1), 5.0, 0.2, 16.0, B,
+                          -int(rng.integers(0, B)), -int(rng.integers(0, B)))
+    g = rng.random((c, h, w))
+    got = fov.backward(torch.from_numpy(g).to(dev), p, layout="CHW").cpu().numpy()
+    ref = orc.adjoint(g, p)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())

@@ -200,3 +200,15 @@ def test_radius_beyond_lds_is_refused(fov, dev):
     with pytest.raises(fov.FoveateError) as ei:
         fov.forward(x, synth.params_dict(0, 0, 0, 10.0, 400.0, 32), layout="CHW")
     assert ei.value.status == -10
+
+
+@pytest.mark.parametrize("B", [64, 1, 3])
+def test_extreme_blocks_f32(fov, orc, dev, B):
+    # the largest fragment side and degenerate tiny ones
+    rng = np.random.default_rng(400 + B)
+    h, w, c = 150, 170, 2
+    x = synth.uniform_frames((c, h, w), seed=B)
+    p = synth.params_dict(rng.uniform(0, w - 1), rng.uniform(0, h - 1), 3.0, 0.1, 12.0, B,
+                          -int(rng.integers(0, B)), -int(rng.integers(0, B)))
+    y = run_chw(fov, dev, x, p)
+    assert np.max(np.abs(y - orc.forward(x.astype(np.float64), p))) <= TOL_F32
