@@ -92,9 +92,19 @@ class FoveateError(RuntimeError):
 
 
 def lib():
-    """Load libfoveate.so; raises if it has not been built (no fallback)."""
+    """Load libfoveate.so; raises if it has not been built (no fallback).
+
+    PyTorch, when installed, is imported first: it brings its own HIP runtime,
+    and the library must resolve its HIP symbols against that same runtime
+    (device pointers and streams come from PyTorch).  Loading the library
+    first would pull the system runtime in beside PyTorch's.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError("libfoveate.so is not built (run paper_2012_08655_amd._build.build()); "
                               "there is no fallback path")

@@ -200,3 +200,16 @@ def test_fragment_shift_matches_oracle(orc):
     assert L.foveate_fragment_shift(1.0, 1.0, 0, ctypes.byref(ox), ctypes.byref(oy)) == N.FOV_EINVAL
     assert L.foveate_fragment_shift(float("nan"), 1.0, 32, ctypes.byref(ox), ctypes.byref(oy)) == N.FOV_EINVAL
     assert L.foveate_fragment_shift(1.0, 1.0, 32, None, ctypes.byref(oy)) == N.FOV_EINVAL
+
+
+def test_library_shares_torchs_hip_runtime():
+    # Loading the library before torch must not put a second HIP runtime in the process
+    # (device pointers and streams come from torch's runtime).
+    import subprocess
+    import sys
+    code = ("import paper_2012_08655_amd as fov; fov.load(); import torch; "
+            "m = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
