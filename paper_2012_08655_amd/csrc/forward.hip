@@ -186,11 +186,31 @@ struct Stager<uint8_t, _Float16> {
     __device__ __forceinline__ void issue(const uint8_t* plane_, int y0_, int rows_) {
         poff = (uint32_t)(plane_ - base);
         y0 = y0_; rows = rows_;
+        if (!cv) return;  // one lane predicate for all rows (not one exec-mask region per row)
         const int wave = wave_id();
+        if (y0 >= 0 && y0 + rows <= h) {
+            // strip inside the frame: row offsets step by 4 rows, no clamping
+            const uint32_t s0 = poff + (uint32_t)(y0 + wave) * ish, step = (uint32_t)(kThreads / 64) * ish;
+            if (rows == kStripMax) {  // full strip: every row of every wave
+#pragma unroll
+                for (int rb = 0; rb < kRowsPerWave; ++rb) {
+                    b0[rb] = load_byte(rsrc, c0, s0 + rb * step);
+                    b1[rb] = load_byte(rsrc, c1, s0 + rb * step);
+                }
+                return;
+            }
+#pragma unroll
+            for (int rb = 0; rb < kRowsPerWave; ++rb)
+                if (wave + rb * (kThreads / 64) < rows) {
+                    b0[rb] = load_byte(rsrc, c0, s0 + rb * step);
+                    b1[rb] = load_byte(rsrc, c1, s0 + rb * step);
+                }
+            return;
+        }
 #pragma unroll
         for (int rb = 0; rb < kRowsPerWave; ++rb) {
             const int ty = wave + rb * (kThreads / 64);
-            if (ty < rows && cv) {
+            if (ty < rows) {
                 const uint32_t soff = poff + (uint32_t)clampi(y0 + ty, 0, h - 1) * ish;
                 b0[rb] = load_byte(rsrc, c0, soff);
                 b1[rb] = load_byte(rsrc, c1, soff);
@@ -199,11 +219,17 @@ struct Stager<uint8_t, _Float16> {
     }
     __device__ __forceinline__ void commit(_Float16* tile, int TP) {
         const int wave = wave_id(), lane = threadIdx.x & 63;
+        if (cv) {
+            half2_t* dst = reinterpret_cast<half2_t*>(tile + wave * TP + 2 * lane);
+            const int step = (kThreads / 64) * TP / 2;  // half2 elements per 4 rows (TP is even)
+            if (rows == kStripMax) {
 #pragma unroll
-        for (int rb = 0; rb < kRowsPerWave; ++rb) {
-            const int ty = wave + rb * (kThreads / 64);
-            if (ty < rows && cv)
-                *reinterpret_cast<half2_t*>(tile + ty * TP + 2 * lane) = bytes_to_half2(b0[rb], b1[rb]);
+                for (int rb = 0; rb < kRowsPerWave; ++rb) dst[rb * step] = bytes_to_half2(b0[rb], b1[rb]);
+            } else {
+#pragma unroll
+                for (int rb = 0; rb < kRowsPerWave; ++rb)
+                    if (wave + rb * (kThreads / 64) < rows) dst[rb * step] = bytes_to_half2(b0[rb], b1[rb]);
+            }
         }
         for (int k0 = 128; k0 < TW; k0 += 128) {
             const int tx = k0 + 2 * lane;
