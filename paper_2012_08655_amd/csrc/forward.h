@@ -35,7 +35,8 @@ struct FwdLaunch {
     int32_t* prefix;     // device array of nframes+1 entries
     const int32_t* hdr;  // optional device header {nframes, nfrag, nslots}: when set, the kernels
                          // read the counts there and the fields above are capacities (a launch
-                         // sequence that can be captured once and replayed for many batches)
+                         // sequence that can be captured once and replayed for many batches; the
+                         // replayer sets the main kernel's grid to the batch's slot count)
     int32_t kprefix[kArgFrames + 1];
     FrameDesc fr[kArgFrames];
 };
@@ -67,6 +68,10 @@ PlanBuffers carve_plan(void* ws, int nfrag, int nslots);
 fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,
                           hipStream_t stream, size_t lds_limit, int cus, bool persist,
                           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+
+// The main forward kernel for a dtype pair and dispatch mode (to find its node
+// in a captured graph); NULL for an unsupported pair.
+const void* forward_main_kernel(int in_dtype, int out_dtype, bool persist);
 
 // Plan kernel alone (radius, order key and normalised taps of every fragment,
 // float taps for wsize 4, double for 8); publishes the frame table when the

@@ -636,7 +636,7 @@ fov_status launch_typed(const FwdLaunch& a, size_t lds, const PlanBuffers& plan,
                        a.split_log2, nrings, nang, a.nslots, a.hdr, plan.order);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "order kernel launch");
-    if (persist || a.hdr) return launch_main<TIn, TOut, TS, TC, true>(a, lds, plan, stream, lds_limit, cus, ev_start, ev_stop);
+    if (persist) return launch_main<TIn, TOut, TS, TC, true>(a, lds, plan, stream, lds_limit, cus, ev_start, ev_stop);
     return launch_main<TIn, TOut, TS, TC, false>(a, lds, plan, stream, lds_limit, cus, ev_start, ev_stop);
 }
 
@@ -687,6 +687,22 @@ fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_
     if (in_dtype == FOV_F64 && out_dtype == FOV_F64)
         return launch_typed<double, double, double, double>(a, lds, plan, stream, lds_limit, cus, persist, ev_start, ev_stop);
     return set_error(FOV_EDTYPE, "unsupported dtype pair");
+}
+
+const void* forward_main_kernel(int in_dtype, int out_dtype, bool persist) {
+    if (in_dtype == FOV_U8 && out_dtype == FOV_U8)
+        return persist ? (const void*)fov_fwd_kernel<uint8_t, uint8_t, _Float16, float, true>
+                       : (const void*)fov_fwd_kernel<uint8_t, uint8_t, _Float16, float, false>;
+    if (in_dtype == FOV_U8 && out_dtype == FOV_F32)
+        return persist ? (const void*)fov_fwd_kernel<uint8_t, float, _Float16, float, true>
+                       : (const void*)fov_fwd_kernel<uint8_t, float, _Float16, float, false>;
+    if (in_dtype == FOV_F32 && out_dtype == FOV_F32)
+        return persist ? (const void*)fov_fwd_kernel<float, float, float, float, true>
+                       : (const void*)fov_fwd_kernel<float, float, float, float, false>;
+    if (in_dtype == FOV_F64 && out_dtype == FOV_F64)
+        return persist ? (const void*)fov_fwd_kernel<double, double, double, double, true>
+                       : (const void*)fov_fwd_kernel<double, double, double, double, false>;
+    return nullptr;
 }
 
 fov_status launch_plan_weights(const FwdLaunch& a, int wsize, const PlanBuffers& plan, hipStream_t stream) {

@@ -58,6 +58,8 @@ struct Slot {
     void* dev = nullptr;    // plan workspace + staged batch table
     void* host = nullptr;   // pinned copy of the staged batch table
     size_t stage_bytes = 0;
+    hipGraphNode_t main_node = nullptr;  // the main kernel's node: its grid is set per batch
+    hipKernelNodeParams main_params{};
 };
 
 struct FakeItem {
@@ -193,7 +195,7 @@ fov_status build_graph(ServerImpl* s, Slot& sl) {
     e = hipMemcpyAsync(const_cast<int32_t*>(a.hdr), sl.host, sl.stage_bytes, hipMemcpyHostToDevice, sl.stream);
     st = e == hipSuccess ? FOV_OK : hip_error(e, "hipMemcpyAsync(batch table)");
     if (st == FOV_OK)
-        st = launch_forward(a, s->cfg.in_dtype, s->cfg.out_dtype, lds, plan, sl.stream, dev->lds_limit, dev->cus, true);
+        st = launch_forward(a, s->cfg.in_dtype, s->cfg.out_dtype, lds, plan, sl.stream, dev->lds_limit, dev->cus, false);
     if (st == FOV_OK) {
         e = hipLaunchHostFunc(sl.stream, on_batch_done, &sl);
         if (e != hipSuccess) st = hip_error(e, "hipLaunchHostFunc");
@@ -206,6 +208,27 @@ fov_status build_graph(ServerImpl* s, Slot& sl) {
     }
     if (e2 != hipSuccess) return hip_error(e2, "hipStreamEndCapture");
     sl.graph = g;
+    // The main kernel was captured with one workgroup per slot of the largest
+    // batch; each replay sets its grid to the batch's own slot count.
+    const void* main_fn = forward_main_kernel(s->cfg.in_dtype, s->cfg.out_dtype, false);
+    size_t nnodes = 0;
+    e = hipGraphGetNodes(g, nullptr, &nnodes);
+    if (e != hipSuccess) return hip_error(e, "hipGraphGetNodes");
+    std::vector<hipGraphNode_t> nodes(nnodes);
+    e = hipGraphGetNodes(g, nodes.data(), &nnodes);
+    if (e != hipSuccess) return hip_error(e, "hipGraphGetNodes");
+    for (hipGraphNode_t n : nodes) {
+        hipGraphNodeType type;
+        if (hipGraphNodeGetType(n, &type) != hipSuccess || type != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        e = hipGraphKernelNodeGetParams(n, &kp);
+        if (e != hipSuccess) return hip_error(e, "hipGraphKernelNodeGetParams");
+        if (kp.func == main_fn) {
+            sl.main_node = n;
+            sl.main_params = kp;
+        }
+    }
+    if (!sl.main_node) return set_error(FOV_EHIP, "captured batch graph has no main kernel node");
     e = hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) return hip_error(e, "hipGraphInstantiate");
     return FOV_OK;
@@ -231,7 +254,10 @@ fov_status launch_batch(ServerImpl* s, Slot& sl, const std::vector<FrameDesc>& f
             acc += frames[i].p.nbx * frames[i].nby;
         }
         pre[frames.size()] = acc;
-        hipError_t e = hipGraphLaunch(sl.exec, sl.stream);
+        sl.main_params.gridDim = dim3((unsigned)hdr.nslots);
+        hipError_t e = hipGraphExecKernelNodeSetParams(sl.exec, sl.main_node, &sl.main_params);
+        if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams");
+        e = hipGraphLaunch(sl.exec, sl.stream);
         if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
         return FOV_OK;
     }
