@@ -16,6 +16,8 @@ struct AdjShape {
     int32_t chunk_c;  // channels the horizontal kernel stages at once
     int32_t pad_b;    // zero rows above and below a staged fragment in the vertical kernel
     int32_t pitch_b;  // LDS column pitch of the vertical kernel
+    int32_t tasks_v;  // vertical kernel: output tasks per thread (1, 2 or 4)
+    int32_t chunk_v;  // vertical kernel: channels staged together
 };
 
 // Leading zero taps before each fragment's weights: windows may start up to

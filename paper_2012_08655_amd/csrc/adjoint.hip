@@ -21,8 +21,9 @@
 //     taps that meet the fragment form one wave-uniform range.
 //  2. fov_adj_v_kernel — one workgroup per output tile (the fragment grid):
 //     for every fragment b whose reach meets the tile, stage b's scratch rows
-//     over the tile's columns (zero-padded) in LDS and accumulate the vertical
-//     transpose in registers; the fragments are visited in a fixed order.
+//     over the tile's columns (zero-padded, several channels at once) in LDS
+//     and accumulate the vertical transpose in registers; the fragments are
+//     visited in a fixed order.
 // Both passes are the forward's register-window correlations with the taps
 // read as scalar operands, run over the band of taps that meet the fragment.
 #include "adjoint.h"
@@ -38,7 +39,6 @@ namespace fov {
 namespace {
 
 constexpr int kPadA = 12;  // zero columns staged before a fragment row (horizontal kernel)
-constexpr int kAdjTasks = (kMaxBlock * (kMaxBlock / kPV) + kThreads - 1) / kThreads;
 
 __global__ void fov_adj_lead_kernel(unsigned char* p, int bytes) {
     for (int i = threadIdx.x; i < bytes; i += blockDim.x) p[i] = 0;
@@ -69,14 +69,14 @@ __global__ __launch_bounds__(kThreads) void fov_adj_h_kernel(const FwdLaunch a, 
         const int cc = min(s.chunk_c, d.c - c0);
         const int RT = cc * F.bh;
         if (c0 > 0) __syncthreads();  // previous channels' rows are no longer read
-        for (int i = tid; i < RT * P; i += kThreads) {
-            const int row = i / P, col = i - row * P;
+        for (int row = wave; row < RT; row += kThreads / 64) {  // a wave per row, lanes along it
             const int k = row / F.bh, py = row - k * F.bh;
-            const int x = col - kPadA;
-            T v = 0;
-            if (x >= 0 && x < F.bw)
-                v = g[(int64_t)(c0 + k) * d.isc + (int64_t)(F.ya + py) * d.ish + (int64_t)(F.xa + x) * d.isw];
-            rows[i] = v;
+            const T* grow = g + (int64_t)(c0 + k) * d.isc + (int64_t)(F.ya + py) * d.ish + (int64_t)F.xa * d.isw;
+            T* lrow = rows + row * P;
+            for (int col = lane; col < P; col += 64) {
+                const int x = col - kPadA;
+                lrow[col] = (x >= 0 && x < F.bw) ? grow[(int64_t)x * d.isw] : (T)0;
+            }
         }
         __syncthreads();
         const int nchunk = (RT + 63) / 64;
@@ -127,7 +127,10 @@ __global__ __launch_bounds__(kThreads) void fov_adj_h_kernel(const FwdLaunch a, 
 }
 
 // Vertical gather into output tile gid: grad_in over the tile's rectangle.
-template <typename T>
+// TASKS: output tasks per thread (4 rows of one column each), CB: channels
+// staged and accumulated together, so each neighbouring fragment costs one
+// staging round per CB channels.
+template <typename T, int TASKS, int CB>
 __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, const AdjShape s,
                                                              const FrameDesc* __restrict__ table,
                                                              const int32_t* __restrict__ prefix,
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, 
                                                              const T* __restrict__ wts,
                                                              const T* __restrict__ scratch) {
     extern __shared__ __align__(16) unsigned char smem[];
-    T* cols = reinterpret_cast<T*>(smem);  // [bmax columns][pitch_b rows]
+    T* cols = reinterpret_cast<T*>(smem);  // [CB channels][bmax columns][pitch_b rows]
     constexpr int V = 16 / sizeof(T);
     const int gid = blockIdx.x;
     const Frag Q = describe(table, prefix, a.nframes, gid);
@@ -146,17 +149,21 @@ __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, 
     const int K = (a.r_cap + fp.block - 1) / fp.block;  // fragments within reach on each side
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
     const int PB = s.pitch_b, PAD = s.pad_b;
+    const int CS = s.bmax * PB;  // one staged channel
     const int ngroups = (Q.bh + kPV - 1) / kPV;
     const int ntask = s.bmax * ngroups;  // task i: column i % bmax, rows 4 (i / bmax) .. +3
     const int by_lo = max(Q.by - K, 0), by_hi = min(Q.by + K, nby - 1);
     const int bx_lo = max(Q.bx - K, 0), bx_hi = min(Q.bx + K, nbx - 1);
     T* out = static_cast<T*>(d.out);
-    for (int c = 0; c < d.c; ++c) {
-        T acc[kAdjTasks][kPV];
+    for (int c0 = 0; c0 < d.c; c0 += CB) {
+        const int cc = min(CB, d.c - c0);
+        T acc[CB][TASKS][kPV];
 #pragma unroll
-        for (int k = 0; k < kAdjTasks; ++k)
+        for (int ch = 0; ch < CB; ++ch)
 #pragma unroll
-            for (int p = 0; p < kPV; ++p) acc[k][p] = 0;
+            for (int k = 0; k < TASKS; ++k)
+#pragma unroll
+                for (int p = 0; p < kPV; ++p) acc[ch][k][p] = 0;
         for (int by = by_lo; by <= by_hi; ++by)
             for (int bx = bx_lo; bx <= bx_hi; ++bx) {
                 const int b = first + by * nbx + bx;
@@ -166,22 +173,24 @@ __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, 
                 const int ry0 = max(Fb.ya - r, 0), ry1 = min(Fb.ya + Fb.bh - 1 + r, d.h - 1);
                 if (rx1 < Q.xa || rx0 >= Q.xa + Q.bw || ry1 < Q.ya || ry0 >= Q.ya + Q.bh) continue;
                 const T* __restrict__ w = wts + (size_t)b * a.wstride;
-                const T* src = scratch + ((size_t)b * s.cmax + c) * s.bmax * s.sw;
                 const int xoff = a.r_cap - Fb.xa;
                 __syncthreads();  // the previous fragment's columns are no longer read
-                // column x of the tile: PAD zero rows, b's rows, zeros to the pitch
+                // per channel, column x of the tile: PAD zero rows, b's rows, zeros to the pitch
                 const int nrg = PB / V;
-                for (int i = tid; i < Q.bw * nrg; i += kThreads) {
-                    const int rg = i / Q.bw, x = i - rg * Q.bw;
+                const int items = Q.bw * nrg;
+                for (int i = tid; i < cc * items; i += kThreads) {
+                    const int ch = i / items, j = i - ch * items;
+                    const int rg = j / Q.bw, x = j - rg * Q.bw;
                     const int gx = Q.xa + x;
                     const bool inx = gx >= rx0 && gx <= rx1;
+                    const T* src = scratch + ((size_t)b * s.cmax + c0 + ch) * s.bmax * s.sw;
                     T v[V];
 #pragma unroll
                     for (int u = 0; u < V; ++u) {
                         const int py = rg * V + u - PAD;
                         v[u] = (inx && py >= 0 && py < Fb.bh) ? src[(size_t)py * s.sw + gx + xoff] : (T)0;
                     }
-                    T* dst = cols + x * PB + rg * V;
+                    T* dst = cols + ch * CS + x * PB + rg * V;
                     if constexpr (V == 4) {
                         *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
                     } else {
@@ -190,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, 
                 }
                 __syncthreads();
 #pragma unroll
-                for (int k = 0; k < kAdjTasks; ++k) {
+                for (int k = 0; k < TASKS; ++k) {
                     const int i0 = wave * 64 + k * kThreads;
                     if (i0 >= ntask) break;
                     // taps t with y + t inside fragment b for some row y of this wave
@@ -198,83 +207,95 @@ __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, 
                     const int ymin = Q.ya + kPV * gA, ymax = min(Q.ya + kPV * gB + kPV - 1, Q.ya + Q.bh - 1);
                     int t_lo = max(-r, Fb.ya - ymax);
                     const int t_hi = min(r, Fb.ya + Fb.bh - 1 - ymin);
+                    if (t_lo <= t_hi) t_lo -= (Q.ya + t_lo - Fb.ya + PAD) & (V - 1);  // aligned window start
                     const int i = i0 + lane;
                     const int x = i % s.bmax, gr = i / s.bmax;
                     if (x >= Q.bw || gr >= ngroups) continue;
                     const int y0 = Q.ya + kPV * gr;
-                    const T* col = cols + x * PB + PAD - Fb.ya;  // col[y]: b's transpose at frame row y
-                    if (t_lo <= t_hi) {
-                        t_lo -= (Q.ya + t_lo - Fb.ya + PAD) & (V - 1);  // aligned window start
-                        vconv(acc[k], col + y0 + t_lo, t_hi - t_lo + 1, w + (t_lo + r));
-                    }
-                    if (y0 == 0) {  // row 0 collects the taps that fell off the top edge
-                        T cdf = 0, corr = 0;
-                        for (int m = -r; m <= -Fb.ya - 1; ++m) {
-                            cdf += w[m + r];
-                            const int py = -m - 1;
-                            if (py < Fb.ya + Fb.bh) corr = fma(cdf, col[py], corr);
-                        }
-                        acc[k][0] += corr;
-                    }
-                    const int pr = d.h - 1 - y0;
-                    if (pr >= 0 && pr < kPV) {  // row h-1 collects those off the bottom edge
-                        T cdf = 0, corr = 0;
-                        for (int m = -r; m <= -1; ++m) {
-                            cdf += w[m + r];
-                            const int py = m + d.h;
-                            if (py >= Fb.ya && py < Fb.ya + Fb.bh) corr = fma(cdf, col[py], corr);
-                        }
+                    const bool top = y0 == 0;           // row 0 collects the taps off the top edge
+                    const int pr = d.h - 1 - y0;        // row h-1 collects those off the bottom edge
+                    const bool bottom = pr >= 0 && pr < kPV;
 #pragma unroll
-                        for (int p = 0; p < kPV; ++p)
-                            if (p == pr) acc[k][p] += corr;
+                    for (int ch = 0; ch < CB; ++ch) {
+                        if (ch >= cc) break;
+                        const T* col = cols + ch * CS + x * PB + PAD - Fb.ya;  // col[y]: b's transpose at row y
+                        if (t_lo <= t_hi) vconv(acc[ch][k], col + y0 + t_lo, t_hi - t_lo + 1, w + (t_lo + r));
+                        if (top) {
+                            T cdf = 0, corr = 0;
+                            for (int m = -r; m <= -Fb.ya - 1; ++m) {
+                                cdf += w[m + r];
+                                const int py = -m - 1;
+                                if (py < Fb.ya + Fb.bh) corr = fma(cdf, col[py], corr);
+                            }
+                            acc[ch][k][0] += corr;
+                        }
+                        if (bottom) {
+                            T cdf = 0, corr = 0;
+                            for (int m = -r; m <= -1; ++m) {
+                                cdf += w[m + r];
+                                const int py = m + d.h;
+                                if (py >= Fb.ya && py < Fb.ya + Fb.bh) corr = fma(cdf, col[py], corr);
+                            }
+#pragma unroll
+                            for (int p = 0; p < kPV; ++p)
+                                if (p == pr) acc[ch][k][p] += corr;
+                        }
                     }
                 }
             }
 #pragma unroll
-        for (int k = 0; k < kAdjTasks; ++k) {
+        for (int k = 0; k < TASKS; ++k) {
             const int i = wave * 64 + k * kThreads + lane;
             if (i >= ntask) break;
             const int x = i % s.bmax, gr = i / s.bmax;
             if (x >= Q.bw || gr >= ngroups) continue;
-            T* o = out + c * d.osc + (int64_t)(Q.xa + x) * d.osw;
 #pragma unroll
-            for (int p = 0; p < kPV; ++p) {
-                const int y = Q.ya + kPV * gr + p;
-                if (y < Q.ya + Q.bh) o[(int64_t)y * d.osh] = acc[k][p];
+            for (int ch = 0; ch < CB; ++ch) {
+                if (ch >= cc) break;
+                T* o = out + (c0 + ch) * d.osc + (int64_t)(Q.xa + x) * d.osw;
+#pragma unroll
+                for (int p = 0; p < kPV; ++p) {
+                    const int y = Q.ya + kPV * gr + p;
+                    if (y < Q.ya + Q.bh) o[(int64_t)y * d.osh] = acc[ch][k][p];
+                }
             }
         }
     }
 }
 
-template <typename T>
+template <typename T, int TASKS, int CB>
 struct AdjSlot {
     static bool configured;
 };
-template <typename T>
-bool AdjSlot<T>::configured = false;
+template <typename T, int TASKS, int CB>
+bool AdjSlot<T, TASKS, CB>::configured = false;
 
-template <typename T>
+fov_status set_dyn_lds(const void* k, size_t lds_limit) {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, k);
+    if (e != hipSuccess) return hip_error(e, "hipFuncGetAttributes(adjoint)");
+    const size_t dyn_max = lds_limit > fa.sharedSizeBytes ? lds_limit - fa.sharedSizeBytes : 0;
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max);
+    if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(adjoint)");
+    return FOV_OK;
+}
+
+template <typename T, int TASKS, int CB>
 fov_status launch_typed(const FwdLaunch& a, const AdjShape& s, const PlanBuffers& plan, void* scratch,
                         hipStream_t stream, size_t lds_limit) {
     auto kh = fov_adj_h_kernel<T>;
-    auto kv = fov_adj_v_kernel<T>;
-    hipError_t e;
-    if (!AdjSlot<T>::configured) {
-        for (const void* k : {(const void*)kh, (const void*)kv}) {
-            hipFuncAttributes fa;
-            e = hipFuncGetAttributes(&fa, k);
-            if (e != hipSuccess) return hip_error(e, "hipFuncGetAttributes(adjoint)");
-            const size_t dyn_max = lds_limit > fa.sharedSizeBytes ? lds_limit - fa.sharedSizeBytes : 0;
-            e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max);
-            if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(adjoint)");
-        }
-        AdjSlot<T>::configured = true;
+    auto kv = fov_adj_v_kernel<T, TASKS, CB>;
+    fov_status st;
+    if (!AdjSlot<T, TASKS, CB>::configured) {
+        if ((st = set_dyn_lds((const void*)kh, lds_limit)) != FOV_OK) return st;
+        if ((st = set_dyn_lds((const void*)kv, lds_limit)) != FOV_OK) return st;
+        AdjSlot<T, TASKS, CB>::configured = true;
     }
     const T* wts = static_cast<const T*>(plan.weights);
     T* sc = static_cast<T*>(scratch);
     hipLaunchKernelGGL(kh, dim3(a.nfrag), dim3(kThreads), adjoint_lds_h(s, sizeof(T)), stream, a, s,
                        (const FrameDesc*)a.table, (const int32_t*)a.prefix, (const int32_t*)plan.radius, wts, sc);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "adjoint horizontal kernel launch");
     hipLaunchKernelGGL(kv, dim3(a.nfrag), dim3(kThreads), adjoint_lds_v(s, sizeof(T)), stream, a, s,
                        (const FrameDesc*)a.table, (const int32_t*)a.prefix, (const int32_t*)plan.radius, wts,
@@ -282,6 +303,14 @@ fov_status launch_typed(const FwdLaunch& a, const AdjShape& s, const PlanBuffers
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "adjoint vertical kernel launch");
     return FOV_OK;
+}
+
+template <typename T>
+fov_status launch_for_tasks(const FwdLaunch& a, const AdjShape& s, const PlanBuffers& plan, void* scratch,
+                            hipStream_t stream, size_t lds_limit) {
+    if (s.tasks_v == 1) return launch_typed<T, 1, 4>(a, s, plan, scratch, stream, lds_limit);
+    if (s.tasks_v == 2) return launch_typed<T, 2, 2>(a, s, plan, scratch, stream, lds_limit);
+    return launch_typed<T, 4, 1>(a, s, plan, scratch, stream, lds_limit);
 }
 
 }  // namespace
@@ -297,12 +326,17 @@ AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax) {
     const int span = std::min(kPV * (63 / bmax + 1) + kPV - 1, bmax - 1);
     s.pad_b = round_up(span + 4, 4);
     s.pitch_b = inter_pitch(bmax + 2 * s.pad_b, es);
+    // vertical kernel: tasks of 4 rows x 1 column per thread (1, 2 or 4) and
+    // channels staged together (4 / tasks, at most the channel count)
+    const int tasks = (bmax * ((bmax + kPV - 1) / kPV) + kThreads - 1) / kThreads;
+    s.tasks_v = tasks <= 1 ? 1 : (tasks <= 2 ? 2 : 4);
+    s.chunk_v = std::max(1, std::min(cmax, 4 / s.tasks_v));
     return s;
 }
 
 size_t adjoint_lds_h(const AdjShape& s, int es) { return (size_t)s.chunk_c * s.bmax * s.pitch_a * es; }
 
-size_t adjoint_lds_v(const AdjShape& s, int es) { return (size_t)s.bmax * s.pitch_b * es; }
+size_t adjoint_lds_v(const AdjShape& s, int es) { return (size_t)s.chunk_v * s.bmax * s.pitch_b * es; }
 
 size_t adjoint_scratch_elems(const AdjShape& s, int nfrag) {
     return (size_t)nfrag * s.cmax * s.bmax * s.sw;
@@ -319,8 +353,8 @@ fov_status launch_adjoint(const FwdLaunch& a, const AdjShape& s, int es, const P
     if (e != hipSuccess) return hip_error(e, "adjoint lead kernel launch");
     fov_status st = launch_plan_weights(a, es, plan, stream);
     if (st != FOV_OK) return st;
-    return es == 8 ? launch_typed<double>(a, s, plan, scratch, stream, lds_limit)
-                   : launch_typed<float>(a, s, plan, scratch, stream, lds_limit);
+    return es == 8 ? launch_for_tasks<double>(a, s, plan, scratch, stream, lds_limit)
+                   : launch_for_tasks<float>(a, s, plan, scratch, stream, lds_limit);
 }
 
 }  // namespace fov
