@@ -2,16 +2,17 @@
 //
 // Three launches per batch of frames on the caller's stream:
 //
-//  1. fov_plan_kernel — one wavefront per fragment: the fragment's sigma from
-//     its midpoint's eccentricity (Sec. 2, Fig. 1), radius r = ceil(3 sigma)
-//     and the normalised taps w_k = exp(-k^2/(2 sigma^2)) / sum (Eq. 1 cut at
-//     3 sigma, Appendix "Methods"), summed with wavefront shuffles, written to
-//     the plan workspace.
+//  1. fov_plan_weights_kernel — one wavefront per fragment: the fragment's
+//     sigma from its midpoint's eccentricity (Sec. 2, Fig. 1), radius
+//     r = ceil(3 sigma) and the normalised taps w_k = exp(-k^2/(2 sigma^2)) / sum
+//     (Eq. 1 cut at 3 sigma, Appendix "Methods"), summed with wavefront
+//     shuffles, written to the plan workspace.
 //
-//  2. fov_order_kernel — a counting sort of fragments by decreasing radius,
-//     the dispatch order of the main kernel (costliest fragments first).
+//  2. fov_order_kernel — a counting sort of fragments by decreasing radius
+//     (costliest first), dealt within each radius in angular arcs to the
+//     eight XCDs: the dispatch order of the main kernel.
 //
-//  3. fov_fwd_kernel — one workgroup per output fragment (Alg. 1): the padded
+//  3. fov_fwd_kernel — one workgroup per work item (Alg. 1): the padded
 //     tile (fragment plus r on each side, clamp-to-edge) is staged into LDS
 //     with row-coalesced loads, 8-bit input kept exact as fp16; a horizontal
 //     pass writes the fp32 intermediate into LDS; a vertical pass produces the
