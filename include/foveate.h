@@ -97,6 +97,26 @@ typedef struct {
 fov_status foveate_grid(int32_t h, int32_t w, const fov_params* p, int32_t* nbx, int32_t* nby);
 
 /*
+ * Geisler-Perry blur model (Appendix "Choosing the Standard Deviation", Eqs.
+ * 3-6) as ramp parameters.  With CT0 = 1/64, alpha = 0.106 and e2 = 2.3 (the
+ * constants the paper adopts), the cutoff f_c_deg(e) = e2 ln(1/CT0) /
+ * (alpha (e + e2)) cycles/degree, f_c_pix = 0.5 f_c_deg / f_max cycles/pixel,
+ * the eccentricity e = d / d_corner * e_corner degrees for a pixel distance d
+ * from the fixation (d_corner = the half-diagonal of an h x w frame in
+ * pixel-centre coordinates), and sigma = 1 / (2 pi f_c_pix).  That sigma is
+ * affine in d, so it is written into p as the ramp's e0 (negative: every
+ * fragment blurs, none is copied), slope and cap:
+ *   sigma(d) = f_max alpha (e_corner d / d_corner + e2) / (pi e2 ln(1/CT0)),
+ * capped at `cap` (> 0; use a large value for none).  f_max (cycles/degree at
+ * the fovea) <= 0 selects f_c_deg(0), for which sigma(0) = 1/pi.  The other
+ * fields of p (fixation, block, origin, sigma_map) are left as they are.
+ * FOV_EINVAL for h, w < 1, a frame of one pixel, e_corner <= 0, a non-finite
+ * argument or cap <= 0.  Host-only arithmetic.
+ */
+fov_status foveate_csf_params(int32_t h, int32_t w, double e_corner_deg, double f_max_cpd, double cap,
+                              fov_params* p);
+
+/*
  * Fragment shift (Alg. 1; Sec. 3 on the SSIM map): the tiling origin that
  * centres one fragment on the fixation, so that the copied fovea is as small
  * as possible and the blur moves with the gaze instead of snapping into place

@@ -15,6 +15,9 @@ adds two NumPy helpers that are themselves definitions:
 * :func:`to_u8` -- the 8-bit output rule: round half to even, clip to 0..255.
 * :func:`fragment_shift` -- the tiling origin that centres one fragment on
   the fixation (Alg. 1, Sec. 3 "SSIM"), in plain Python.
+* :func:`csf_sigma` / :func:`csf_sigma_map` -- the Geisler-Perry blur model
+  (Appendix "Choosing the Standard Deviation", Eqs. 3-6) evaluated step by
+  step in NumPy, per distance or per fragment midpoint.
 
 Arrays are [c, h, w] (or [n, c, h, w]) float64; frame parameters are plain
 dicts with keys fix_x, fix_y, e0, slope, cap, block, origin_x, origin_y.
@@ -133,6 +136,48 @@ def fragment_shift(p: Mapping) -> dict:
         o = start % B  # Python's modulo: 0 .. B-1
         out["origin_" + axis] = o - B if o > 0 else 0
     return out
+
+
+# Contrast-threshold model constants the paper adopts (Eq. 3 and the text after it).
+CSF_CT0 = 1.0 / 64.0
+CSF_ALPHA = 0.106
+CSF_E2 = 2.3
+
+
+def csf_contrast_threshold(f_cpd, e_deg):
+    """Eq. 3: contrast needed to detect a grating of f cycles/degree at
+    eccentricity e degrees."""
+    return CSF_CT0 * np.exp(CSF_ALPHA * f_cpd * (e_deg + CSF_E2) / CSF_E2)
+
+
+def csf_cutoff_cpd(e_deg):
+    """Eq. 4: the frequency whose threshold is full contrast (CT = 1)."""
+    return CSF_E2 / (CSF_ALPHA * (e_deg + CSF_E2)) * np.log(1.0 / CSF_CT0)
+
+
+def csf_sigma(d_px, h: int, w: int, e_corner: float, f_max: float = 0.0):
+    """sigma (pixels) at pixel distance d from the fixation, for an h x w frame
+    whose corner is e_corner degrees away (Eqs. 4-6).  f_max <= 0 takes the
+    foveal cutoff f_c_deg(0) as the highest resolvable frequency."""
+    if f_max <= 0:
+        f_max = csf_cutoff_cpd(0.0)
+    d_corner = np.hypot((w - 1) / 2.0, (h - 1) / 2.0)  # half-diagonal, pixel-centre coordinates
+    e = np.asarray(d_px, dtype=np.float64) / d_corner * e_corner  # Eq. 5
+    f_c_deg = csf_cutoff_cpd(e)  # Eq. 4
+    f_c_pix = 0.5 * f_c_deg / f_max  # cycles per pixel
+    return 1.0 / (2.0 * np.pi * f_c_pix)  # Eq. 6
+
+
+def csf_sigma_map(h: int, w: int, p: Mapping, e_corner: float, f_max: float = 0.0, cap: float = 1e6):
+    """Per-fragment sigma [nby, nbx] from each fragment midpoint's distance to
+    the fixation (midpoints as in the ramp plan), capped at cap."""
+    nby, nbx = grid(h, w, p)
+    B = int(p.get("block", 32))
+    half = (B - 1) / 2.0
+    cy = p.get("origin_y", 0) + np.arange(nby) * B + half
+    cx = p.get("origin_x", 0) + np.arange(nbx) * B + half
+    d = np.hypot(cx[None, :] - p["fix_x"], cy[:, None] - p["fix_y"])
+    return np.minimum(csf_sigma(d, h, w, e_corner, f_max), cap)
 
 
 def plan(h: int, w: int, p: Mapping, sigma_map=None) -> tuple[np.ndarray, np.ndarray]:

@@ -19,7 +19,7 @@ def __getattr__(name):
     # checking its exports) does not require torch.
     if name in ("forward", "forward_batch", "backward", "grid", "plan_device", "plan_host", "foveate", "FoveateFn",
                 "tensor_desc", "profile_begin", "profile_end", "autotune", "autotune_batch", "tuning_force",
-                "tuning_clear", "tuning_count", "tuning_save", "tuning_load", "fragment_shift"):
+                "tuning_clear", "tuning_count", "tuning_save", "tuning_load", "fragment_shift", "csf_params"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

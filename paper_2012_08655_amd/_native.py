@@ -55,6 +55,8 @@ SIGNATURES = {
     "foveate_grid": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _PP, _I32P, _I32P]),
     "foveate_plan": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _PP, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]),
+    "foveate_csf_params": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, _PP]),
     "foveate_fragment_shift": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int32, _I32P, _I32P]),
     "foveate_plan_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _PP, ctypes.c_void_p, ctypes.c_void_p]),
     "foveate_forward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),

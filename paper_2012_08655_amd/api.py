@@ -213,6 +213,17 @@ def grid(h: int, w: int, params: Mapping) -> tuple[int, int]:
     return nby.value, nbx.value
 
 
+def csf_params(h: int, w: int, params: Mapping, e_corner: float, f_max: float = 0.0, cap: float = 1e6) -> dict:
+    """Copy of ``params`` whose ramp (e0, slope, cap) is the Geisler-Perry
+    blur model for an h x w frame whose corner sits at ``e_corner`` degrees
+    (foveate_csf_params)."""
+    p = N.make_params(params)
+    N.check(N.lib().foveate_csf_params(int(h), int(w), float(e_corner), float(f_max), float(cap), ctypes.byref(p)))
+    out = dict(params)
+    out["e0"], out["slope"], out["cap"] = p.e0, p.slope, p.cap
+    return out
+
+
 def fragment_shift(params: Mapping) -> dict:
     """Copy of ``params`` with the tiling origin that centres one fragment on
     the fixation (foveate_fragment_shift)."""

@@ -591,6 +591,27 @@ fov_status foveate_grid(int32_t h, int32_t w, const fov_params* p, int32_t* nbx,
     return FOV_OK;
 }
 
+fov_status foveate_csf_params(int32_t h, int32_t w, double e_corner_deg, double f_max_cpd, double cap,
+                              fov_params* p) {
+    if (!p) return set_error(FOV_EINVAL, "p is NULL");
+    if (h < 1 || w < 1 || (h == 1 && w == 1)) return set_error(FOV_EINVAL, "frame must have at least two pixels");
+    if (!std::isfinite(e_corner_deg) || e_corner_deg <= 0) return set_error(FOV_EINVAL, "e_corner must be > 0");
+    if (!std::isfinite(f_max_cpd) || !std::isfinite(cap) || cap <= 0)
+        return set_error(FOV_EINVAL, "f_max must be finite and cap > 0");
+    // constants of the contrast-threshold model the paper adopts (Eq. 3)
+    const double ct0 = 1.0 / 64.0, alpha = 0.106, e2 = 2.3;
+    const double ln_inv_ct0 = std::log(1.0 / ct0);
+    const double f_max = f_max_cpd > 0 ? f_max_cpd : ln_inv_ct0 / alpha;  // f_c_deg at e = 0
+    const double hx = 0.5 * (w - 1), hy = 0.5 * (h - 1);
+    const double d_corner = std::sqrt(hx * hx + hy * hy);
+    // sigma(d) = k (e_corner d / d_corner + e2) = slope (d - e0)
+    const double k = f_max * alpha / (M_PI * e2 * ln_inv_ct0);
+    p->slope = k * e_corner_deg / d_corner;
+    p->e0 = -e2 * d_corner / e_corner_deg;
+    p->cap = cap;
+    return FOV_OK;
+}
+
 fov_status foveate_fragment_shift(double fix_x, double fix_y, int32_t block, int32_t* origin_x,
                                   int32_t* origin_y) {
     if (!origin_x || !origin_y) return set_error(FOV_EINVAL, "NULL argument");

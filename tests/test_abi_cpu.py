@@ -213,3 +213,33 @@ def test_library_shares_torchs_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_csf_params_reproduce_the_oracle_model(orc):
+    L = N.lib()
+    rng = np.random.default_rng(31)
+    for _ in range(20):
+        h, w = int(rng.integers(2, 2200)), int(rng.integers(2, 4000))
+        ec, cap = float(rng.uniform(5, 60)), float(rng.uniform(2, 30))
+        fmax = float(rng.choice([0.0, rng.uniform(10, 60)]))
+        B = int(rng.choice([8, 16, 32]))
+        base = synth.params_dict(rng.uniform(0, w - 1), rng.uniform(0, h - 1), 0, 0, 0, B)
+        p = N.make_params(base)
+        assert L.foveate_csf_params(h, w, ec, fmax, cap, ctypes.byref(p)) == N.FOV_OK
+        assert p.e0 < 0
+        q = dict(base, e0=p.e0, slope=p.slope, cap=p.cap)
+        nby, nbx = orc.grid(h, w, q)
+        sig = np.zeros(nby * nbx)
+        rad = np.zeros(nby * nbx, np.int32)
+        arr = (N.FovParams * 1)(N.make_params(q))
+        assert L.foveate_plan_host(h, w, arr, sig.ctypes.data_as(ctypes.c_void_p),
+                                   rad.ctypes.data_as(ctypes.c_void_p)) == N.FOV_OK
+        ref = orc.csf_sigma_map(h, w, base, ec, fmax, cap).reshape(-1)
+        assert np.max(np.abs(sig - ref) / ref) <= 1e-12
+        rr = np.ceil(3 * ref)
+        near = np.abs(3 * ref - np.round(3 * ref)) < 1e-9
+        assert np.all((rad == rr) | near)
+    p = N.make_params(P0)
+    assert L.foveate_csf_params(1, 1, 10.0, 0.0, 8.0, ctypes.byref(p)) == N.FOV_EINVAL
+    assert L.foveate_csf_params(10, 10, 0.0, 0.0, 8.0, ctypes.byref(p)) == N.FOV_EINVAL
+    assert L.foveate_csf_params(10, 10, 10.0, 0.0, 0.0, ctypes.byref(p)) == N.FOV_EINVAL

@@ -292,3 +292,42 @@ def test_fragment_shift_makes_blur_follow_the_gaze(orc):
     z0 = orc.forward(x, base)
     z1 = orc.forward(_translate_cols(x, k), shifted)
     assert np.max(np.abs(z1[..., r + k:120 - r] - z0[..., r:120 - k - r])) > 1e-3
+
+
+# ---- Geisler-Perry blur model (Appendix "Choosing the Standard Deviation", Eqs. 3-6) ------------
+
+def test_csf_cutoff_inverts_the_contrast_threshold(orc):
+    # Eq. 4 is Eq. 3 solved for CT = 1 (full contrast)
+    for e in (0.0, 0.5, 2.3, 10.0, 45.0):
+        assert abs(orc.csf_contrast_threshold(orc.csf_cutoff_cpd(e), e) - 1.0) <= 1e-12
+    # and a slightly higher frequency needs more than full contrast
+    assert orc.csf_contrast_threshold(1.01 * orc.csf_cutoff_cpd(5.0), 5.0) > 1.0
+
+
+def test_csf_sigma_closed_forms(orc):
+    # With f_max = f_c_deg(0): sigma = (e + e2) / (pi e2), so 1/pi at the fixation and
+    # (e_corner + e2) / (pi e2) at the half-diagonal; a given f_max scales sigma by f_max / f_c_deg(0).
+    h, w, ec = 1080, 1920, 30.0
+    dc = math.hypot(959.5, 539.5)
+    assert abs(orc.csf_sigma(0.0, h, w, ec) - 1.0 / math.pi) <= 1e-15
+    assert abs(orc.csf_sigma(dc, h, w, ec) - (ec + 2.3) / (math.pi * 2.3)) <= 1e-12
+    f0 = math.log(64.0) / 0.106
+    assert abs(orc.csf_cutoff_cpd(0.0) - f0) <= 1e-12
+    assert abs(orc.csf_sigma(dc / 2, h, w, ec, f_max=20.0) / orc.csf_sigma(dc / 2, h, w, ec) - 20.0 / f0) <= 1e-12
+    # sigma is affine in the pixel distance (Eq. 5 is linear, Eq. 4 is 1/(e + e2))
+    d = np.linspace(0, 1500, 7)
+    s = orc.csf_sigma(d, h, w, ec)
+    assert np.max(np.abs(np.diff(s, 2))) <= 1e-12
+
+
+def test_csf_sigma_map_midpoints(orc):
+    # 16 px fragments with a shifted grid: columns start at -5, 11, 27 (w = 30) and rows at
+    # -3, 13, 29 (h = 40); midpoints worked by hand
+    p = synth.params_dict(20.0, 10.0, 0, 0, 0, 16, -5, -3)
+    m = orc.csf_sigma_map(40, 30, p, 20.0)
+    assert m.shape == (3, 3)
+    for by in range(3):
+        for bx in range(3):
+            cx, cy = -5 + 16 * bx + 7.5, -3 + 16 * by + 7.5
+            assert abs(m[by, bx] - orc.csf_sigma(math.hypot(cx - 20.0, cy - 10.0), 40, 30, 20.0)) <= 1e-15
+    assert np.all(orc.csf_sigma_map(40, 30, p, 20.0, cap=0.5) <= 0.5)
