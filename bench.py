@@ -287,6 +287,57 @@ def batch_leg(reps=10, seed=11):
                                 "mpix_s": round(mpix / med_p * 1e3, 1)}}
 
 
+def host_pipeline_leg(frames=300, slots=3, seed=13):
+    """End-to-end rate with the frames in pinned host memory (the paper's
+    165 Hz includes its transfers): per frame an H2D copy on one stream, the
+    foveation on the compute stream, a D2H copy on a third stream, ordered by
+    events and overlapped across frames through `slots` device buffers."""
+    import torch
+    import synth
+    import paper_2012_08655_amd as fov
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    src = torch.from_numpy(synth.grating_frame(H, W, C, seed=seed)).pin_memory()
+    host_in = [src.clone().pin_memory() for _ in range(slots)]
+    host_out = [torch.empty_like(src).pin_memory() for _ in range(slots)]
+    d_in = [torch.empty(src.shape, dtype=torch.uint8, device=dev) for _ in range(slots)]
+    d_out = [torch.empty_like(t) for t in d_in]
+    params = [synth.params_cfg2(rng) for _ in range(frames)]
+    s_h2d, s_d2h = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+    comp = torch.cuda.current_stream()
+    h2d_done = [torch.cuda.Event() for _ in range(slots)]
+    fwd_done = [torch.cuda.Event() for _ in range(slots)]
+    d2h_done = [torch.cuda.Event() for _ in range(slots)]
+
+    def run(n):
+        for i in range(n):
+            k = i % slots
+            if i >= slots:
+                s_h2d.wait_event(fwd_done[k])  # the forward of frame i - slots has read d_in[k]
+            with torch.cuda.stream(s_h2d):
+                d_in[k].copy_(host_in[k], non_blocking=True)
+                h2d_done[k].record(s_h2d)
+            comp.wait_event(h2d_done[k])
+            if i >= slots:
+                comp.wait_event(d2h_done[k])  # the D2H of frame i - slots has read d_out[k]
+            fov.forward(d_in[k], params[i], out=d_out[k], layout="HWC", stream=comp)
+            fwd_done[k].record(comp)
+            s_d2h.wait_event(fwd_done[k])
+            with torch.cuda.stream(s_d2h):
+                host_out[k].copy_(d_out[k], non_blocking=True)
+                d2h_done[k].record(s_d2h)
+        torch.cuda.synchronize()
+
+    run(2 * slots)
+    t0 = time.perf_counter()
+    run(frames)
+    wall = time.perf_counter() - t0
+    return {"frames": frames, "device_buffers": slots, "fps": round(frames / wall, 1),
+            "ms_per_frame": round(wall * 1e3 / frames, 4), "mpix_s": round(frames * H * W / wall / 1e6, 1),
+            "transfer": "pinned host u8 HWC 1920x1080x3 in and out, H2D / D2H on two copy streams",
+            "paper_context": "165 Hz on a GTX 1060 including transfers"}
+
+
 def adjoint_leg(reps=20, seed=12):
     """Forward and adjoint (foveate_backward) on training-style batches:
     32 x 3x224x224 and 4 x 3x512x512 float32, fixation uniform over the image,
@@ -441,6 +492,8 @@ def main():
         result["batch"] = batch_leg()
         print("bench: adjoint leg", file=sys.stderr, flush=True)
         result["adjoint"] = adjoint_leg()
+        print("bench: host pipeline leg", file=sys.stderr, flush=True)
+        result["host_pipeline"] = host_pipeline_leg()
     if not args.no_serve:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
         result["serving"] = serving_leg(rates, args.serve_seconds, 0.5, args.serve_budget_mib, args.serve_max_batch,
