@@ -237,6 +237,65 @@ void orc_forward_points(const double* in, int c, int h, int w, const orc_frame* 
 }
 
 /*
+ * "Perfect" foveation, the reference of the paper's quality comparison (Sec. 3,
+ * Fig. 3): every pixel is blurred with its own sigma, from its own distance to
+ * the fixation (pixel-centre coordinates) through the same ramp, instead of
+ * its fragment midpoint's.  The window is Eq. (1) normalised over the square
+ * (2r+1)^2 grid, i.e. the outer product of the normalised 1-D taps g, and the
+ * sum is taken row by row: out = sum_i g(i) sum_j g(j) in(clamp(y+i), clamp(x+j)).
+ * The tiling fields of f (block, origin) and the sigma map do not apply.
+ */
+void orc_forward_per_pixel(const double* in, double* out, int c, int h, int w, const orc_frame* f, int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = 0; y < h; ++y) {
+        double* g = NULL;
+        int gcap = 0;
+        for (int x = 0; x < w; ++x) {
+            double dx = (double)x - f->fix_x, dy = (double)y - f->fix_y;
+            double e = sqrt(dx * dx + dy * dy);
+            double sigma = 0.0;
+            if (!(e < f->e0)) {
+                sigma = f->slope * (e - f->e0);
+                if (sigma > f->cap) sigma = f->cap;
+                if (!(sigma > 0.0)) sigma = 0.0;
+            }
+            int r = orc_radius(sigma);
+            if (r == 0) {
+                for (int ch = 0; ch < c; ++ch)
+                    out[((size_t)ch * h + y) * w + x] = in[((size_t)ch * h + y) * w + x];
+                continue;
+            }
+            int n = 2 * r + 1;
+            if (n > gcap) {
+                free(g);
+                g = (double*)malloc(sizeof(double) * (size_t)n);
+                gcap = n;
+            }
+            double s = 0.0;
+            for (int i = -r; i <= r; ++i) {
+                g[i + r] = exp(-((double)(i * i)) / (2.0 * sigma * sigma));
+                s += g[i + r];
+            }
+            for (int i = 0; i < n; ++i) g[i] /= s;
+            for (int ch = 0; ch < c; ++ch) {
+                const double* plane = in + (size_t)ch * h * w;
+                double acc = 0.0;
+                for (int i = -r; i <= r; ++i) {
+                    const double* row = plane + (size_t)clampi(y + i, 0, h - 1) * w;
+                    double racc = 0.0;
+                    for (int j = -r; j <= r; ++j) racc += g[j + r] * row[clampi(x + j, 0, w - 1)];
+                    acc += g[i + r] * racc;
+                }
+                out[((size_t)ch * h + y) * w + x] = acc;
+            }
+        }
+        free(g);
+    }
+}
+
+/*
  * Adjoint (transpose) of the forward map, by its definition
  *     (A^T g)(q) = sum_p A(p, q) g(p):
  * every output pixel p scatters g(p) * W(i,j) onto the clamped input pixel it

@@ -76,6 +76,7 @@ def _load():
         lib.orc_forward_points.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, dp,
                                            ip, ip, ctypes.c_int, dp, ctypes.c_int]
         lib.orc_adjoint.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, dp, ctypes.c_int]
+        lib.orc_forward_per_pixel.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, ctypes.c_int]
         lib.orc_eq7_shared_bytes.argtypes = [ctypes.c_int, ctypes.c_int]
         lib.orc_eq7_shared_bytes.restype = ctypes.c_long
         lib.orc_max_threads.restype = ctypes.c_int
@@ -204,6 +205,17 @@ def forward(x: np.ndarray, params, sigma_map=None, nthreads: int = 0) -> np.ndar
     f = _frame(params)
     m, mp = _map_arg(sigma_map)
     _load().orc_forward(_dptr(x), _dptr(out), c, h, w, ctypes.byref(f), mp, int(nthreads))
+    return out
+
+
+def forward_per_pixel(x: np.ndarray, params: Mapping, nthreads: int = 0) -> np.ndarray:
+    """'Perfect' foveation of a [c,h,w] frame: every pixel blurred with the
+    ramp's sigma at its own distance from the fixation (Sec. 3, Fig. 3)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    c, h, w = x.shape
+    out = np.empty_like(x)
+    f = _frame(params)
+    _load().orc_forward_per_pixel(_dptr(x), _dptr(out), c, h, w, ctypes.byref(f), int(nthreads))
     return out
 
 

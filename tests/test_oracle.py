@@ -331,3 +331,45 @@ def test_csf_sigma_map_midpoints(orc):
             cx, cy = -5 + 16 * bx + 7.5, -3 + 16 * by + 7.5
             assert abs(m[by, bx] - orc.csf_sigma(math.hypot(cx - 20.0, cy - 10.0), 40, 30, 20.0)) <= 1e-15
     assert np.all(orc.csf_sigma_map(40, 30, p, 20.0, cap=0.5) <= 0.5)
+
+
+# ---- per-pixel ("perfect") foveation and SSIM (Sec. 3, Fig. 3) -----------------------------------
+
+def test_per_pixel_equals_blockwise_with_one_pixel_fragments(orc):
+    # a fragment of one pixel has its midpoint at the pixel centre
+    x = synth.uniform_frames((2, 40, 52), seed=3).astype(np.float64)
+    p = synth.params_dict(20.3, 14.8, 3.0, 0.15, 5.0, 1)
+    assert np.max(np.abs(orc.forward_per_pixel(x, p) - orc.forward(x, p))) <= 1e-12
+
+
+def test_per_pixel_uniform_sigma_matches_scipy(orc):
+    # the ramp saturated at the cap everywhere: one Gaussian for the whole frame
+    x = synth.uniform_frames((1, 37, 45), seed=4).astype(np.float64)
+    s = 2.3
+    p = synth.params_dict(10.0, 10.0, -1e6, 1.0, s)
+    ref = ndi.gaussian_filter(x[0], s, mode="nearest", radius=int(math.ceil(3 * s)))
+    assert np.max(np.abs(orc.forward_per_pixel(x, p)[0] - ref)) <= 1e-12
+
+
+def test_ssim_definition():
+    from oracle.ssim import ssim_map
+    rng = np.random.default_rng(6)
+    a = rng.uniform(0, 255, (40, 50))
+    assert np.allclose(ssim_map(a, a), 1.0, atol=1e-12)
+    b = np.clip(a + rng.normal(0, 20, a.shape), 0, 255)
+    m = ssim_map(a, b)
+    assert np.allclose(m, ssim_map(b, a), atol=1e-12) and np.all(m < 1.0)
+    # constant images: the variance terms vanish, SSIM = (2ab + C1) / (a^2 + b^2 + C1)
+    c1 = (0.01 * 255) ** 2
+    m = ssim_map(np.full((20, 20), 100.0), np.full((20, 20), 120.0))
+    assert np.allclose(m, (2 * 100 * 120 + c1) / (100 ** 2 + 120 ** 2 + c1), atol=1e-12)
+    # brute force at an interior pixel with the explicit 11 x 11 normalised Gaussian window
+    y0, x0 = 20, 25
+    k = np.exp(-np.arange(-5, 6) ** 2 / (2 * 1.5 ** 2))
+    win = np.outer(k, k) / np.outer(k, k).sum()
+    pa, pb = a[y0 - 5:y0 + 6, x0 - 5:x0 + 6], b[y0 - 5:y0 + 6, x0 - 5:x0 + 6]
+    mx, my = (win * pa).sum(), (win * pb).sum()
+    sxx, syy, sxy = (win * pa * pa).sum() - mx * mx, (win * pb * pb).sum() - my * my, (win * pa * pb).sum() - mx * my
+    c2 = (0.03 * 255) ** 2
+    ref = (2 * mx * my + c1) * (2 * sxy + c2) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+    assert abs(ssim_map(a, b)[y0, x0] - ref) <= 1e-10
