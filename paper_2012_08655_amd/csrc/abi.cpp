@@ -85,12 +85,18 @@ std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 }  // namespace
 
-fov_status workspace(hipStream_t stream, size_t dev_bytes, size_t host_bytes, Workspace** out) {
+fov_status workspace(hipStream_t stream, size_t dev_bytes, size_t host_bytes, Workspace** out,
+                     std::unique_lock<std::mutex>* hold) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_error(e, "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    Workspace& w = g_ws[{dev, stream}];
+    Workspace* wp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);  // map entries never move or disappear
+        wp = &g_ws[{dev, stream}];
+    }
+    Workspace& w = *wp;
+    *hold = std::unique_lock<std::mutex>(w.mu);
     if (w.dev_bytes < dev_bytes) {
         if (w.dev) {
             e = hipStreamSynchronize(stream);
@@ -382,7 +388,8 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     const bool upload = nf > kArgFrames;
     const size_t tbytes = frame_table_bytes(nf);
     Workspace* ws = nullptr;
-    if ((s = workspace(stream, pbytes + tbytes, upload ? tbytes : 0, &ws)) != FOV_OK) return s;
+    std::unique_lock<std::mutex> hold;
+    if ((s = workspace(stream, pbytes + tbytes, upload ? tbytes : 0, &ws, &hold)) != FOV_OK) return s;
     const PlanBuffers plan = carve_plan(ws->dev, a.nfrag, a.nslots);
     if ((s = stage_frame_table(frames.data(), nf, prefix.data(), ws, static_cast<char*>(ws->dev) + pbytes, tbytes,
                                stream, &a)) != FOV_OK)
@@ -429,7 +436,9 @@ fov_status run_backward_group(const FrameDesc* frames, int nf, int dtype, hipStr
     const size_t tbytes = frame_table_bytes(nf);
     const size_t sbytes = adjoint_scratch_elems(sh, a.nfrag) * es;
     Workspace* ws = nullptr;
-    if ((s = workspace(stream, 2 * f4 + wbytes + tbytes + sbytes, nf > kArgFrames ? tbytes : 0, &ws)) != FOV_OK)
+    std::unique_lock<std::mutex> hold;
+    if ((s = workspace(stream, 2 * f4 + wbytes + tbytes + sbytes, nf > kArgFrames ? tbytes : 0, &ws, &hold)) !=
+        FOV_OK)
         return s;
     char* base = static_cast<char*>(ws->dev);
     PlanBuffers plan;

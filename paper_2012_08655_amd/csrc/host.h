@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,7 @@ fov_status device_info(const DeviceInfo** out);
 // Per-(device, stream) workspace: device buffer for plans and frame tables,
 // pinned host buffer for table uploads (see abi.cpp).
 struct Workspace {
+    std::mutex mu;  // held by a call from lookup (and any growth) until its launches are enqueued
     void* dev = nullptr;
     size_t dev_bytes = 0;
     void* host = nullptr;
@@ -29,7 +31,12 @@ struct Workspace {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
 };
-fov_status workspace(hipStream_t stream, size_t dev_bytes, size_t host_bytes, Workspace** out);
+// The workspace of (current device, stream), grown to at least the given
+// sizes, returned with its mutex locked in *hold: host threads that share a
+// stream take turns, so none enqueues work with pointers into a buffer
+// another thread has just replaced.
+fov_status workspace(hipStream_t stream, size_t dev_bytes, size_t host_bytes, Workspace** out,
+                     std::unique_lock<std::mutex>* hold);
 
 const std::string& last_error();
 int env_int(const char* name, int dflt);
