@@ -14,12 +14,14 @@ pytestmark = pytest.mark.gpu
 
 def test_threads_sharing_a_stream(fov, dev):
     stream = torch.cuda.Stream(device=dev)
-    sizes = [(40, 60), (300, 500), (90, 70), (700, 900), (33, 47), (520, 610)]
+    # the 4K frames need a plan workspace of several MiB, so the workspace grows under load
+    sizes = [(40, 60), (2160, 3840), (90, 70), (700, 900), (33, 47), (1500, 2600)]
+    g = torch.Generator(device=dev).manual_seed(3)
     jobs = []
     for i in range(24):
         h, w = sizes[i % len(sizes)]
-        x = torch.from_numpy(synth.grating_frame(h, w, 3, seed=60 + i)).to(dev)
-        p = synth.params_dict(w / 2, h / 2, 5.0, 0.05, 8.0)
+        x = torch.randint(0, 256, (h, w, 3), dtype=torch.uint8, device=dev, generator=g)
+        p = synth.params_dict(w / 2, h / 2, 5.0, 0.05, 16.0)
         jobs.append((x, p))
     ref = [fov.forward(x, p, layout="HWC") for x, p in jobs]
     torch.cuda.synchronize()
