@@ -200,10 +200,15 @@ fov_status foveate_backward(const fov_tensor* grad_out, const fov_tensor* grad_i
  *                once: 16, 32 or 64.  Fewer rows need less LDS per workgroup.
  *   persistent : 1 = a grid sized to what the chip holds at once strides
  *                over the work queue; 0 = one workgroup per queue slot.
+ *   merge      : 1 = a fragment on an even row whose sigma and the sigma of
+ *                the fragment below both equal the cap is one work item with
+ *                it (equal taps: the halo rows the two share are computed
+ *                once); needs split 1.  By default it is on unless its taller
+ *                tiles would let fewer workgroups share a CU.
  *   time_us    : (output of foveate_autotune) median time of one call.
  */
 typedef struct {
-    int32_t split, strip_rows, persistent;
+    int32_t split, strip_rows, persistent, merge;
     float time_us;
 } fov_tuning;
 
@@ -216,7 +221,8 @@ typedef struct {
  * side, the bit length of the largest radius, the bit length of the fragment
  * count and the frame-count class (1, 2..16, more).  Later forward calls of
  * that class, from any thread, use the cached configuration; others use the
- * defaults (split 1, 64 strip rows, one workgroup per queue slot).  Writes
+ * defaults (split 1, 64 strip rows, one workgroup per queue slot, merge as
+ * described above).  Writes
  * the chosen configuration to *best (may be NULL).  Arguments and errors as
  * foveate_forward / foveate_forward_batch; `out` holds the foveated frames on
  * return.  Synchronises `stream`.
@@ -229,7 +235,7 @@ fov_status foveate_autotune_batch(const fov_tensor* ins, const fov_tensor* outs,
 /*
  * Force one configuration for the forward calls of the calling thread
  * (tests, experiments); NULL returns the thread to the cache and defaults.
- * FOV_EINVAL for values outside the sets above.  A forced configuration whose
+ * FOV_EINVAL for values outside the sets above (or merge 1 with a split).  A forced configuration whose
  * LDS does not fit makes the forward call fail with FOV_ERANGE.
  */
 fov_status foveate_tuning_force(const fov_tuning* t);

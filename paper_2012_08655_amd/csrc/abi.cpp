@@ -370,7 +370,18 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     const int r_cap = cs.r_cap;
     const int tile = (cs.bmax + (1 << L) - 1) >> L;
     const int sr = cfg.strip_rows;
-    const size_t lds = forward_lds_bytes(in_dtype, r_cap, tile, sr);
+    size_t lds = forward_lds_bytes(in_dtype, r_cap, tile, tile, sr);
+    // vertical pairs at the cap need tiles twice as tall; by default only when the CU holds as
+    // many workgroups with them
+    bool merge = cfg.merge != 0 && L == 0 && r_cap > 0;
+    if (merge) {
+        const size_t lds2 = forward_lds_bytes(in_dtype, r_cap, tile, 2 * tile, sr);
+        if (lds2 + 64 > dev->lds_limit ||
+            (cfg.merge < 0 && forward_occupancy(in_dtype, out_dtype, lds2) < forward_occupancy(in_dtype, out_dtype, lds)))
+            merge = false;
+        else
+            lds = lds2;
+    }
     if (lds + 64 > dev->lds_limit)
         return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
                                          " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
@@ -380,6 +391,7 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     a.nframes = nf;
     a.nfrag = (int32_t)total;
     a.split_log2 = L;
+    a.merge = merge ? 1 : 0;
     a.r_cap = r_cap;
     a.strip_rows = sr;
     a.wstride = round_up(2 * r_cap + 1, 16);

@@ -31,6 +31,9 @@ struct FwdLaunch {
     int32_t wstride;     // weights per fragment in the plan workspace (multiple of 16)
     int32_t from_args;   // 1: fr[]/kprefix[] hold the frames and the plan kernel
                          // copies them to table/prefix; 0: table/prefix were uploaded
+    int32_t merge;       // 1: a fragment at an even row whose sigma and the sigma of the fragment
+                         // below both equal the cap becomes one work item with it (equal taps, so
+                         // the halo rows they share are computed once); split_log2 must be 0
     FrameDesc* table;    // device table of nframes entries (read by the main kernel)
     int32_t* prefix;     // device array of nframes+1 entries
     const int32_t* hdr;  // optional device header {nframes, nfrag, nslots}: when set, the kernels
@@ -82,12 +85,17 @@ fov_status launch_plan_weights(const FwdLaunch& a, int wsize, const PlanBuffers&
 fov_status launch_plan(const FrameParams& fp, int nblk, double* sigma_out, int32_t* r_out, hipStream_t stream);
 
 // LDS bytes a forward workgroup needs for radius r_cap and output tiles of
-// side `tile` (the fragment side B divided by the split, rounded up).
-size_t forward_lds_bytes(int in_dtype, int r_cap, int tile, int strip_rows);
+// tile_w x tile_h pixels (the fragment side B divided by the split, rounded
+// up; tile_h = 2B when vertical pairs are merged).
+size_t forward_lds_bytes(int in_dtype, int r_cap, int tile_w, int tile_h, int strip_rows);
 
-// Padded-tile rows of a tile of side `tile` at radius r (what a strip height
-// above it cannot change).
-int forward_tile_rows(int r, int tile);
+// Padded-tile rows of a tile tile_h pixels tall at radius r (what a strip
+// height above it cannot change).
+int forward_tile_rows(int r, int tile_h);
+
+// Workgroups of the main kernel (one workgroup per queue slot) that one CU
+// holds at once with `lds` bytes of dynamic LDS each.
+int forward_occupancy(int in_dtype, int out_dtype, size_t lds);
 
 // Largest strip height the kernel stages at once.
 int forward_strip_max();

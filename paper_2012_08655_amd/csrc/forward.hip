@@ -33,6 +33,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 namespace fov {
 
@@ -379,8 +381,13 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
             continue;
         }
         const int gid = item >> (2 * L);
-        const int r = radius[gid];
+        const int rr = radius[gid];
+        const int r = rr & 0xFFFF;
         Frag F = describe(table, prefix, nframes, gid);
+        if (rr >> 16) {  // merged with the fragment below (same taps): one taller tile
+            const Frag F2 = describe_at(F.fd, gid - F.lb, gid + F.fd->p.nbx);
+            F.bh = F2.ya + F2.bh - F.ya;
+        }
         if (!narrow_to_tile(F, L, item & ((1 << (2 * L)) - 1))) {
             if (!PERSIST) break;
             continue;
@@ -441,9 +448,21 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
                                       : fragment_sigma_ramp(fp, F.bx, F.by);
     int r = radius_of(sigma);
     if (r > a.r_cap) r = a.r_cap;  // the host sized everything for r_cap; plans agree bit for bit
+    // Vertical pairs at the cap (rows 2k and 2k+1, both sigma == cap, hence equal taps): the upper
+    // fragment's item covers both, the lower one gets no item.
+    int pair = 0;  // 1: upper of a merged pair, -1: lower
+    if (a.merge && r > 0 && sigma == fp.cap) {
+        const int by2 = F.by ^ 1;
+        if (by2 < F.fd->nby) {
+            const double s2 = fp.sigma_map ? clip_map_sigma((double)fp.sigma_map[F.lb + (by2 - F.by) * fp.nbx], fp.cap)
+                                           : fragment_sigma_ramp(fp, F.bx, by2);
+            if (s2 == fp.cap) pair = (F.by & 1) ? -1 : 1;
+        }
+    }
     if (lane == 0) {
-        radius[gid] = r;
-        okey[gid] = (nrings - 1 - min(r, nrings - 1)) * nang + angle_bin(F, nang);  // (ring, angle bin) cell
+        radius[gid] = r | (pair == 1 ? 0x10000 : 0);
+        okey[gid] = pair == -1 ? -1  // no queue slot
+                               : (nrings - 1 - min(r, nrings - 1)) * nang + angle_bin(F, nang);  // (ring, angle bin)
     }
     const int N = 2 * r + 1;
     const double inv = r > 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
@@ -507,7 +526,10 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
     const int ncell = nrings * nang;
     for (int i = tid; i < ncell; i += kOrderThreads) cells[i] = 0;
     __syncthreads();
-    for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&cells[okey[i >> (2 * L)]], 1);
+    for (int i = tid; i < n; i += kOrderThreads) {
+        const int key = okey[i >> (2 * L)];
+        if (key >= 0) atomicAdd(&cells[key], 1);  // -1: the lower fragment of a merged pair
+    }
     __syncthreads();
     // exclusive scan of the angle bins inside each ring (one wave per ring)
     for (int ring = wave; ring < nrings; ring += kOrderThreads / 64) {
@@ -545,6 +567,7 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
     __syncthreads();
     for (int i = tid; i < n; i += kOrderThreads) {
         const int key = okey[i >> (2 * L)];
+        if (key < 0) continue;
         const int ring = key / nang;
         const int j = atomicAdd(&cells[key], 1);  // rank in the ring
         const int m = ring_n[ring];
@@ -665,10 +688,10 @@ PlanBuffers carve_plan(void* ws, int nfrag, int nslots) {
 
 int forward_strip_max() { return kStripMax; }
 
-int forward_tile_rows(int r, int tile) { return geom(r, tile, tile).TH; }
+int forward_tile_rows(int r, int tile_h) { return geom(r, 1, tile_h).TH; }
 
-size_t forward_lds_bytes(int in_dtype, int r_cap, int tile, int strip_rows) {
-    const Geom g = geom(r_cap, tile, tile);
+size_t forward_lds_bytes(int in_dtype, int r_cap, int tile_w, int tile_h, int strip_rows) {
+    const Geom g = geom(r_cap, tile_w, tile_h);
     int rows = strip_rows < g.TH ? strip_rows : g.TH;
     if (rows > kStripMax) rows = kStripMax;
     const int es = stage_size(in_dtype), ec = compute_size(in_dtype);
@@ -688,6 +711,23 @@ fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_
     if (in_dtype == FOV_F64 && out_dtype == FOV_F64)
         return launch_typed<double, double, double, double>(a, lds, plan, stream, lds_limit, cus, persist, ev_start, ev_stop);
     return set_error(FOV_EDTYPE, "unsupported dtype pair");
+}
+
+int forward_occupancy(int in_dtype, int out_dtype, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, size_t>, int> cache;
+    const void* k = forward_main_kernel(in_dtype, out_dtype, false);
+    if (!k) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({k, lds});
+    if (it != cache.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kThreads, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        nb = 0;
+    }
+    cache[{k, lds}] = nb;
+    return nb;
 }
 
 const void* forward_main_kernel(int in_dtype, int out_dtype, bool persist) {

@@ -56,6 +56,7 @@ struct LaunchCfg {
     int split_log2 = 0;
     int strip_rows = 64;
     bool persistent = false;
+    int merge = -1;  // vertical pairs at the cap as one item: 1 on, 0 off, -1 on unless it lowers occupancy
 };
 
 // What a forward call launches: largest radius and fragment side, fragments.

@@ -188,7 +188,7 @@ fov_status build_graph(ServerImpl* s, Slot& sl) {
     std::memset(sl.host, 0, sl.stage_bytes);
     PlanBuffers plan;
     const FwdLaunch a = capacity_launch(s, sl, &plan);
-    const size_t lds = forward_lds_bytes(s->cfg.in_dtype, s->r_cap, s->cfg.max_block, a.strip_rows);
+    const size_t lds = forward_lds_bytes(s->cfg.in_dtype, s->r_cap, s->cfg.max_block, s->cfg.max_block, a.strip_rows);
     if (lds + 64 > dev->lds_limit) return set_error(FOV_ERANGE, "max_sigma needs more LDS than a workgroup may use");
     e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");

@@ -2,9 +2,10 @@
 // configuration, and the autotuner that times every configuration that fits
 // and caches the fastest for the call's workload class.
 //
-// The choices (output tile split, strip height, dispatch mode) change how
-// fragments map onto workgroups, never the arithmetic of an output pixel, so
-// the cache can be consulted freely: results are the same bit for bit.
+// The choices (output tile split, strip height, dispatch mode, merged pairs of
+// capped fragments) change how fragments map onto workgroups, never the
+// arithmetic of an output pixel, so the cache can be consulted freely: results
+// are the same bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,13 +72,15 @@ LaunchCfg default_cfg() {
     c.split_log2 = 0;
     c.strip_rows = choose_strip_rows();
     c.persistent = dispatch_persistent();
+    c.merge = -1;
     return c;
 }
 
 bool valid_public(const fov_tuning& t) {
     return (t.split == 1 || t.split == 2 || t.split == 4) &&
            (t.strip_rows == 16 || t.strip_rows == 32 || t.strip_rows == 64) &&
-           (t.persistent == 0 || t.persistent == 1);
+           (t.persistent == 0 || t.persistent == 1) && (t.merge == 0 || t.merge == 1) &&
+           !(t.merge == 1 && t.split != 1);
 }
 
 LaunchCfg from_public(const fov_tuning& t) {
@@ -85,6 +88,7 @@ LaunchCfg from_public(const fov_tuning& t) {
     c.split_log2 = t.split == 4 ? 2 : (t.split == 2 ? 1 : 0);
     c.strip_rows = t.strip_rows;
     c.persistent = t.persistent != 0;
+    c.merge = t.merge;
     return c;
 }
 
@@ -93,6 +97,7 @@ fov_tuning to_public(const LaunchCfg& c, float us) {
     t.split = 1 << c.split_log2;
     t.strip_rows = c.strip_rows;
     t.persistent = c.persistent ? 1 : 0;
+    t.merge = c.merge > 0 ? 1 : 0;
     t.time_us = us;
     return t;
 }
@@ -105,19 +110,24 @@ std::vector<LaunchCfg> candidates(const DeviceInfo& dev, int in_dtype, const Cal
     for (int L = 0; L <= 2; ++L) {
         const int tile = (cs.bmax + (1 << L) - 1) >> L;
         if (L > 0 && (tile < 8 || tile == cs.bmax)) break;
-        const int rows = forward_tile_rows(cs.r_cap, tile);
-        int prev = -1;
-        for (int sr : {16, 32, 64}) {
-            const int eff = std::min(sr, rows);
-            if (eff == prev) continue;
-            prev = eff;
-            if (forward_lds_bytes(in_dtype, cs.r_cap, tile, sr) + 64 > dev.lds_limit) continue;
-            for (bool persist : {false, true}) {
-                LaunchCfg c;
-                c.split_log2 = L;
-                c.strip_rows = sr;
-                c.persistent = persist;
-                out.push_back(c);
+        for (int merge : {0, 1}) {
+            if (merge && (L > 0 || cs.r_cap == 0)) continue;
+            const int th = merge ? 2 * tile : tile;
+            const int rows = forward_tile_rows(cs.r_cap, th);
+            int prev = -1;
+            for (int sr : {16, 32, 64}) {
+                const int eff = std::min(sr, rows);
+                if (eff == prev) continue;
+                prev = eff;
+                if (forward_lds_bytes(in_dtype, cs.r_cap, tile, th, sr) + 64 > dev.lds_limit) continue;
+                for (bool persist : {false, true}) {
+                    LaunchCfg c;
+                    c.split_log2 = L;
+                    c.strip_rows = sr;
+                    c.persistent = persist;
+                    c.merge = merge;
+                    out.push_back(c);
+                }
             }
         }
     }
@@ -202,7 +212,7 @@ fov_status autotune_frames(const std::vector<FrameDesc>& frames, int in_dtype, i
     return FOV_OK;
 }
 
-constexpr const char* kTag = "fov-tune-v1";
+constexpr const char* kTag = "fov-tune-v2";
 
 }  // namespace
 
@@ -278,13 +288,13 @@ fov_status foveate_tuning_save(const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return set_error(FOV_EINVAL, std::string("cannot open ") + path + " for writing");
     std::fprintf(f, "# %s arch cus in_dtype out_dtype channels block r_bits frag_bits frames_class : split strip_rows "
-                    "persistent time_us\n", kTag);
+                    "persistent merge time_us\n", kTag);
     for (const auto& kv : copy) {
         const TuneKey& k = kv.first;
         const fov_tuning t = to_public(kv.second.cfg, kv.second.us);
-        std::fprintf(f, "%s %s %d %d %d %d %d %d %d %d : %d %d %d %.3f\n", kTag, k.arch.c_str(), k.cus, k.in_dtype,
+        std::fprintf(f, "%s %s %d %d %d %d %d %d %d %d : %d %d %d %d %.3f\n", kTag, k.arch.c_str(), k.cus, k.in_dtype,
                      k.out_dtype, k.c, k.bmax, k.r_bits, k.frag_bits, k.frames_class, t.split, t.strip_rows,
-                     t.persistent, (double)t.time_us);
+                     t.persistent, t.merge, (double)t.time_us);
     }
     const bool ok = std::fclose(f) == 0;
     if (!ok) return set_error(FOV_EINVAL, std::string("error writing ") + path);
@@ -313,10 +323,10 @@ fov_status foveate_tuning_load(const char* path) {
         fov_tuning t;
         double us = 0.0;
         int used = 0;
-        const int got = std::sscanf(p, "%31s %63s %d %d %d %d %d %d %d %d : %d %d %d %lf %n", tag, arch, &k.cus,
+        const int got = std::sscanf(p, "%31s %63s %d %d %d %d %d %d %d %d : %d %d %d %d %lf %n", tag, arch, &k.cus,
                                     &k.in_dtype, &k.out_dtype, &k.c, &k.bmax, &k.r_bits, &k.frag_bits,
-                                    &k.frames_class, &t.split, &t.strip_rows, &t.persistent, &us, &used);
-        if (got != 14 || std::strcmp(tag, kTag) != 0 || p[used] != '\0' || !valid_public(t) || k.cus < 1 ||
+                                    &k.frames_class, &t.split, &t.strip_rows, &t.persistent, &t.merge, &us, &used);
+        if (got != 15 || std::strcmp(tag, kTag) != 0 || p[used] != '\0' || !valid_public(t) || k.cus < 1 ||
             k.in_dtype < 0 || k.in_dtype > 2 || k.out_dtype < 0 || k.out_dtype > 2 || k.c < 1 || k.bmax < 1 ||
             k.bmax > kMaxBlock || k.r_bits < 0 || k.r_bits > 31 || k.frag_bits < 0 || k.frag_bits > 62 ||
             k.frames_class < 0 || k.frames_class > 2 || !(us >= 0.0)) {

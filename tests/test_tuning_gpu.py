@@ -11,20 +11,21 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = list(itertools.product((1, 2, 4), (16, 32, 64), (0, 1)))
+CONFIGS = [(sp, sr, pe, mg) for sp, sr, pe, mg in itertools.product((1, 2, 4), (16, 32, 64), (0, 1), (0, 1))
+           if not (mg and sp != 1)]
 
 
 def run_all_configs(fov, fn):
     base = fn()
     torch.cuda.synchronize()
-    for split, sr, persist in CONFIGS:
-        fov.tuning_force(split, sr, persist)
+    for split, sr, persist, merge in CONFIGS:
+        fov.tuning_force(split, sr, persist, merge)
         try:
             got = fn()
             torch.cuda.synchronize()
         finally:
             fov.tuning_force(None)
-        assert torch.equal(got, base), (split, sr, persist)
+        assert torch.equal(got, base), (split, sr, persist, merge)
     return base
 
 
@@ -65,6 +66,7 @@ def test_autotune_caches_and_matches(fov, dev, tmp_path):
     best = fov.autotune(x, p, out=out, layout="HWC", reps=3)
     torch.cuda.synchronize()
     assert best["split"] in (1, 2, 4) and best["strip_rows"] in (16, 32, 64) and best["persistent"] in (0, 1)
+    assert best["merge"] in (0, 1)
     assert best["time_us"] > 0
     assert torch.equal(out, ref)
     assert fov.tuning_count() == 1
