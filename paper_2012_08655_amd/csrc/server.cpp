@@ -149,9 +149,10 @@ void fake_device_loop(ServerImpl* s) {
 }
 
 // Capacity launch of the replayable batch step of one slot.
-FwdLaunch capacity_launch(const ServerImpl* s, const Slot& sl, PlanBuffers* plan) {
+FwdLaunch capacity_launch(const ServerImpl* s, const Slot& sl, PlanBuffers* plan, bool merge) {
     FwdLaunch a;
     std::memset(&a, 0, sizeof(a));
+    a.merge = merge ? 1 : 0;
     a.nframes = s->cfg.max_batch_frames;
     a.nfrag = s->cfg.max_fragments;
     a.nslots = queue_slots(a.nfrag, s->r_cap);
@@ -186,10 +187,18 @@ fov_status build_graph(ServerImpl* s, Slot& sl) {
     e = hipHostMalloc(&sl.host, sl.stage_bytes, hipHostMallocDefault);
     if (e != hipSuccess) return set_error(FOV_ENOMEM, "server staging allocation failed");
     std::memset(sl.host, 0, sl.stage_bytes);
-    PlanBuffers plan;
-    const FwdLaunch a = capacity_launch(s, sl, &plan);
-    const size_t lds = forward_lds_bytes(s->cfg.in_dtype, s->r_cap, s->cfg.max_block, s->cfg.max_block, a.strip_rows);
+    // capped vertical pairs as one item (as the plain forward does by default) when the taller
+    // tiles let as many workgroups share a CU
+    const int B = s->cfg.max_block, sr = choose_strip_rows();
+    size_t lds = forward_lds_bytes(s->cfg.in_dtype, s->r_cap, B, B, sr);
     if (lds + 64 > dev->lds_limit) return set_error(FOV_ERANGE, "max_sigma needs more LDS than a workgroup may use");
+    const size_t lds2 = forward_lds_bytes(s->cfg.in_dtype, s->r_cap, B, 2 * B, sr);
+    const bool merge = s->r_cap > 0 && lds2 + 64 <= dev->lds_limit &&
+                       forward_occupancy(s->cfg.in_dtype, s->cfg.out_dtype, lds2) >=
+                           forward_occupancy(s->cfg.in_dtype, s->cfg.out_dtype, lds);
+    if (merge) lds = lds2;
+    PlanBuffers plan;
+    const FwdLaunch a = capacity_launch(s, sl, &plan, merge);
     e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
     e = hipMemcpyAsync(const_cast<int32_t*>(a.hdr), sl.host, sl.stage_bytes, hipMemcpyHostToDevice, sl.stream);
