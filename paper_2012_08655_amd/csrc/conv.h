@@ -144,6 +144,108 @@ __device__ __forceinline__ void hconv(TC (&acc)[kPH], const TS* row, int N, cons
     hstep_part(left, acc, C, A, B, w + j0);
 }
 
+// ---- symmetric horizontal pass for 8-bit input staged as fp16 ----------------------------------
+// The taps are symmetric (w_{-k} = w_k), so out[p] = w_0 x[p] + sum_k w_k (x[p-k] + x[p+k]).  The
+// staged values are integers 0..255 in fp16, so a packed fp16 add forms two such pair sums exactly
+// (at most 510), and one v_fma_mix_f32 per output and distance multiplies a sum by the FP32 weight:
+// 4.5 adds and 8 FMAs per distance for 8 outputs instead of 16 FMAs.  Two samples of a 32-bit
+// register are the outputs (2q, 2q+1) at even distances and (2q-1, 2q) at odd ones; with the
+// centre of output 0 on a 4-sample boundary every operand is a whole register.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ h2v as_h2(uint32_t u) { return __builtin_bit_cast(h2v, u); }
+
+__device__ __forceinline__ uint2 load_grp(const _Float16* p) { return *reinterpret_cast<const uint2*>(p); }
+
+// Distance k: l[q] holds samples (p-k, p+1-k) and t[q] samples (p+k, p+1+k) of the output pair
+// starting at p = 2q (even k) or p = 2q-1 (odd k).
+template <bool ODD>
+__device__ __forceinline__ void sym_tap(float (&acc)[kPH], const uint32_t* l, const uint32_t* t, float wk) {
+    if constexpr (ODD) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const h2v s = as_h2(l[q]) + as_h2(t[q]);
+            if (q > 0) acc[2 * q - 1] = fmaf(wk, (float)s.x, acc[2 * q - 1]);
+            if (q < 4) acc[2 * q] = fmaf(wk, (float)s.y, acc[2 * q]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const h2v s = as_h2(l[q]) + as_h2(t[q]);
+            acc[2 * q] = fmaf(wk, (float)s.x, acc[2 * q]);
+            acc[2 * q + 1] = fmaf(wk, (float)s.y, acc[2 * q + 1]);
+        }
+    }
+}
+
+// Distances 4m+1 .. 4m+NT.  Left groups L0 < L1 < L2 hold samples c-4m-4 .. c-4m+7 and right
+// groups R0 < R1 < R2 samples c+4m .. c+4m+11 (c: centre of output 0).
+template <int NT>
+__device__ __forceinline__ void sym_block(float (&acc)[kPH], uint2 L0, uint2 L1, uint2 L2, uint2 R0, uint2 R1,
+                                          uint2 R2, const float* __restrict__ wk) {
+    const uint32_t l[6] = {L0.x, L0.y, L1.x, L1.y, L2.x, L2.y};
+    const uint32_t t[6] = {R0.x, R0.y, R1.x, R1.y, R2.x, R2.y};
+    if (NT >= 1) sym_tap<true>(acc, l + 1, t, wk[0]);
+    if (NT >= 2) sym_tap<false>(acc, l + 1, t + 1, wk[1]);
+    if (NT >= 3) sym_tap<true>(acc, l, t + 1, wk[2]);
+    if (NT >= 4) sym_tap<false>(acc, l, t + 2, wk[3]);
+}
+
+__device__ __forceinline__ void sym_part(int nt, float (&acc)[kPH], uint2 L0, uint2 L1, uint2 L2, uint2 R0, uint2 R1,
+                                         uint2 R2, const float* __restrict__ wk) {
+    if (nt == 1) sym_block<1>(acc, L0, L1, L2, R0, R1, R2, wk);
+    else if (nt == 2) sym_block<2>(acc, L0, L1, L2, R0, R1, R2, wk);
+    else sym_block<3>(acc, L0, L1, L2, R0, R1, R2, wk);
+}
+
+// 8 horizontal outputs, radius r >= 1.  rc points at the centre of output 0 (8-byte aligned);
+// wc[k] = w_k for k = 0..r.  Reads samples rc[-r-3 .. r+10]: the ones outside [-r, r+7] fall in
+// halves whose sums no output uses.  Sums are taken in the order k = 0, 1, .., r.
+__device__ __forceinline__ void hconv_sym(float (&acc)[kPH], const _Float16* rc, int r, const float* __restrict__ wc) {
+    uint2 LA = load_grp(rc), LB = load_grp(rc + 4), LC;
+    uint2 RA = LA, RB = LB, RC;
+    {
+        const float w0 = wc[0];
+        const uint32_t x[4] = {LA.x, LA.y, LB.x, LB.y};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[2 * q] = fmaf(w0, (float)as_h2(x[q]).x, acc[2 * q]);
+            acc[2 * q + 1] = fmaf(w0, (float)as_h2(x[q]).y, acc[2 * q + 1]);
+        }
+    }
+    // Three buffers per side rotate through a 3-block unrolled loop: block m loads the left group
+    // at c-4m-4 and the right group at c+4m+8 into the buffers the previous block released.
+    const int M = r >> 2, NT = r & 3;
+    int m = 0;
+    for (; m + 3 <= M; m += 3) {
+        LC = load_grp(rc - 4 * (m + 1));
+        RC = load_grp(rc + 4 * (m + 2));
+        sym_block<4>(acc, LC, LA, LB, RA, RB, RC, wc + 4 * m + 1);
+        LB = load_grp(rc - 4 * (m + 2));
+        RA = load_grp(rc + 4 * (m + 3));
+        sym_block<4>(acc, LB, LC, LA, RB, RC, RA, wc + 4 * m + 5);
+        LA = load_grp(rc - 4 * (m + 3));
+        RB = load_grp(rc + 4 * (m + 4));
+        sym_block<4>(acc, LA, LB, LC, RC, RA, RB, wc + 4 * m + 9);
+    }
+    if (m == M && NT == 0) return;
+    LC = load_grp(rc - 4 * (m + 1));
+    RC = load_grp(rc + 4 * (m + 2));
+    if (m == M) { sym_part(NT, acc, LC, LA, LB, RA, RB, RC, wc + 4 * m + 1); return; }
+    sym_block<4>(acc, LC, LA, LB, RA, RB, RC, wc + 4 * m + 1);
+    ++m;
+    if (m == M && NT == 0) return;
+    LB = load_grp(rc - 4 * (m + 1));
+    RA = load_grp(rc + 4 * (m + 2));
+    if (m == M) { sym_part(NT, acc, LB, LC, LA, RB, RC, RA, wc + 4 * m + 1); return; }
+    sym_block<4>(acc, LB, LC, LA, RB, RC, RA, wc + 4 * m + 1);
+    ++m;
+    if (NT == 0) return;  // m == M here
+    LA = load_grp(rc - 4 * (m + 1));
+    RB = load_grp(rc + 4 * (m + 2));
+    sym_part(NT, acc, LA, LB, LC, RC, RA, RB, wc + 4 * m + 1);
+}
+
 template <typename TC>
 __device__ __forceinline__ void vstep_part(int nt, TC (&acc)[kPV], const TC (&X)[4], const TC (&Y)[4],
                                            const TC* __restrict__ w) {

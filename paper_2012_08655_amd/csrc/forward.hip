@@ -20,9 +20,13 @@
 //     thread computes 8 (horizontal) or 4 (vertical) outputs and slides the
 //     filter window through registers (the register reuse of Appendix "Data
 //     Reuse"); the weights are read with scalar loads and used as SGPR
-//     operands of the FMAs.  A fragment with r = 0 is copied.
+//     operands of the FMAs.  For 8-bit input the horizontal pass adds the
+//     two samples that share a weight (the taps are symmetric) exactly in
+//     packed fp16 before the FP32 multiply-add.  A fragment with r = 0 is
+//     copied.
 //
-// Every output sums its taps in the same order (k = -r .. r) whatever the
+// Every output sums its taps in the same order (k = -r .. r; for 8-bit input
+// the horizontal pass goes k = 0, then the pairs +-1 .. +-r) whatever the
 // strip height, output tile split or dispatch mode, so results do not depend
 // on tuning choices.
 #include "forward.h"
@@ -35,6 +39,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 namespace fov {
 
@@ -83,6 +88,9 @@ __device__ __forceinline__ TOut copy_out(TIn v) { return (TOut)v; }
 // arithmetic.  Columns beyond the prefetched chunks are loaded and written
 // inside commit().
 constexpr int kStripMax = 64;
+// Bytes of LDS before the tile: the symmetric horizontal pass may read (and ignore) up to three
+// samples before a row's first one.
+constexpr int kTileLead = 16;
 constexpr int kRowsPerWave = kStripMax / (kThreads / 64);
 
 template <typename TIn, typename TS>
@@ -298,17 +306,22 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
     const TC* __restrict__ w = wts + (size_t)gid * a.wstride;
     const Geom g = geom(r, F.bw, F.bh);
     const int SR = min(min(a.strip_rows, kStripMax), g.TH);
-    const int TP = tile_pitch(g.TW, sizeof(TS));
+    // 8-bit input: the symmetric horizontal pass wants each output's centre on a 4-sample group,
+    // so the tile starts sh = (-r) mod 4 columns further left.
+    constexpr bool kSym = std::is_same<TS, _Float16>::value;
+    const int sh = kSym ? ((-r) & 3) : 0;
+    const int TW = g.TW + sh;
+    const int TP = tile_pitch(TW, sizeof(TS));
     const int IP = inter_pitch(g.TH, sizeof(TC));
-    TS* tile = reinterpret_cast<TS*>(smem);
-    TC* inter = reinterpret_cast<TC*>(smem + align16((size_t)SR * TP * sizeof(TS)));  // [column][row]
+    TS* tile = reinterpret_cast<TS*>(smem + kTileLead);
+    TC* inter = reinterpret_cast<TC*>(smem + kTileLead + align16((size_t)SR * TP * sizeof(TS)));  // [column][row]
     const TIn* in = static_cast<const TIn*>(d.in);
     TOut* out = static_cast<TOut*>(d.out);
     const int nst = (g.TH + SR - 1) / SR;
     const int nunits = d.c * nst;
     Stager<TIn, TS> st;
     const int64_t span = (int64_t)(d.c - 1) * d.isc + (int64_t)(d.h - 1) * d.ish + (int64_t)(d.w - 1) * d.isw + 1;
-    st.setup(F.xa - r, g.TW, d.w, d.isw, d.ish, d.h, in, (uint32_t)span);
+    st.setup(F.xa - r - sh, TW, d.w, d.isw, d.ish, d.h, in, (uint32_t)span);
     st.issue(in, F.ya - r, SR);
     st.commit(tile, TP);
     __syncthreads();
@@ -329,7 +342,8 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
             TC acc[kPH];
 #pragma unroll
             for (int p = 0; p < kPH; ++p) acc[p] = 0;
-            hconv(acc, tile + ty * TP + x0, g.N, w);
+            if constexpr (kSym) hconv_sym(acc, tile + ty * TP + x0 + r + sh, r, w + r);
+            else hconv(acc, tile + ty * TP + x0, g.N, w);
             TC* dst = inter + x0 * IP + s0 + ty;
 #pragma unroll
             for (int p = 0; p < kPH; ++p) dst[p * IP] = acc[p];
@@ -695,7 +709,9 @@ size_t forward_lds_bytes(int in_dtype, int r_cap, int tile_w, int tile_h, int st
     int rows = strip_rows < g.TH ? strip_rows : g.TH;
     if (rows > kStripMax) rows = kStripMax;
     const int es = stage_size(in_dtype), ec = compute_size(in_dtype);
-    return align16((size_t)rows * tile_pitch(g.TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec + 64;
+    // 8-bit input: (-r) mod 4 leading columns; 2r + ((-r) mod 4) never decreases with r, so r_cap sizes them
+    const int TW = g.TW + (in_dtype == FOV_U8 ? ((-r_cap) & 3) : 0);
+    return kTileLead + align16((size_t)rows * tile_pitch(TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec + 64;
 }
 
 fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,

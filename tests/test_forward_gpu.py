@@ -212,3 +212,22 @@ def test_extreme_blocks_f32(fov, orc, dev, B):
                           -int(rng.integers(0, B)), -int(rng.integers(0, B)))
     y = run_chw(fov, dev, x, p)
     assert np.max(np.abs(y - orc.forward(x.astype(np.float64), p))) <= TOL_F32
+
+
+def test_u8_every_radius_phase(fov, orc, dev):
+    # 8-bit input takes the symmetric horizontal pass, whose register rotation and
+    # tail depend on r mod 4 and on (r div 4) mod 3: every radius 1..26 plus a few
+    # near the 1080p cap, all fragments at one sigma (cap), ragged tiles, shifted grid.
+    fr = synth.grating_frame(70, 100, 3, seed=21)
+    t = torch.from_numpy(fr).to(dev)
+    x64 = fr.transpose(2, 0, 1).astype(np.float64)
+    for r in list(range(1, 27)) + [45, 46, 47, 48, 49, 50]:
+        p = synth.params_dict(37.25, 20.5, 0.0, 100.0, (r - 0.5) / 3.0, 32, -5, -9)
+        yf = fov.forward(t, p, layout="HWC", out_dtype=torch.float32)
+        y8 = fov.forward(t, p, layout="HWC")
+        torch.cuda.synchronize()
+        ref = orc.forward(x64, p).transpose(1, 2, 0)
+        err = np.max(np.abs(yf.cpu().numpy() - ref))
+        assert err <= TOL_F32 * 255, (r, err)
+        d = np.abs(y8.cpu().numpy().astype(np.int32) - orc.to_u8(ref).astype(np.int32))
+        assert d.max() <= 1, r
