@@ -340,16 +340,26 @@ fov_status foveate_server_destroy(fov_server* s);
 
 /*
  * Kernel timing for measurement.  Between foveate_profile_begin(capacity) and
- * foveate_profile_end(), each forward call made by this thread records a pair
- * of HIP events on its stream right before and right after its main kernel
- * (the per-fragment blur; the plan and order kernels that precede it are not
- * included), up to `capacity` calls.  foveate_profile_end waits for the
+ * foveate_profile_end(), each forward call made by this thread records the
+ * start and end of its main kernel (the per-fragment blur; the plan and order
+ * kernels that precede it are not included) in a pair of HIP events that the
+ * kernel's dispatch stamps on its stream, up to `capacity` calls.  foveate_profile_end waits for the
  * recorded events, writes up to `capacity` durations in milliseconds to ms
  * (host array, may be NULL), stores how many in *count and releases the
  * events.  FOV_EINVAL if profiling was not started.
  */
 fov_status foveate_profile_begin(int32_t capacity);
 fov_status foveate_profile_end(float* ms, int32_t capacity, int32_t* count);
+
+/*
+ * Record only one forward call in `every` (the 1st, every+1-th, ...) of the
+ * profile window started by foveate_profile_begin on this thread (default 1):
+ * the calls in between run without events.  The main kernel's events are
+ * stamped by its dispatch, which then does not overlap the next kernel of the
+ * stream; sampling keeps that cost off most calls of a throughput run.
+ * FOV_EINVAL if every < 1 or profiling was not started.
+ */
+fov_status foveate_profile_every(int32_t every);
 
 /* Thread-local message for the last non-OK status of this thread ("" if none). */
 const char* foveate_last_error(void);

@@ -73,6 +73,7 @@ SIGNATURES = {
     "foveate_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
     "foveate_profile_begin": (ctypes.c_int, [ctypes.c_int32]),
     "foveate_profile_end": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _I32P]),
+    "foveate_profile_every": (ctypes.c_int, [ctypes.c_int32]),
     "foveate_now": (ctypes.c_double, []),
     "foveate_stream_timestamp": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "foveate_server_create": (ctypes.c_int, [ctypes.POINTER(FovServerCfg), ctypes.POINTER(ctypes.c_void_p)]),

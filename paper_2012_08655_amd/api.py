@@ -193,9 +193,12 @@ def backward(grad_out: torch.Tensor, params, grad_in: torch.Tensor | None = None
     return grad_in
 
 
-def profile_begin(capacity: int):
-    """Start recording main-kernel durations of this thread's forward calls."""
+def profile_begin(capacity: int, every: int = 1):
+    """Start recording main-kernel durations of this thread's forward calls
+    (one call in ``every``)."""
     N.check(N.lib().foveate_profile_begin(int(capacity)))
+    if every != 1:
+        N.check(N.lib().foveate_profile_every(int(every)))
 
 
 def profile_end(capacity: int) -> np.ndarray:

@@ -243,6 +243,8 @@ struct Profiler {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     size_t used = 0;
+    size_t calls = 0;  // forward calls since foveate_profile_begin
+    int every = 1;     // record one call in `every`
 };
 thread_local Profiler g_prof;
 
@@ -253,6 +255,8 @@ void profile_release() {
     }
     g_prof.ev.clear();
     g_prof.used = 0;
+    g_prof.calls = 0;
+    g_prof.every = 1;
     g_prof.on = false;
 }
 }  // namespace
@@ -407,7 +411,7 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
                                stream, &a)) != FOV_OK)
         return s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (profile && g_prof.on && g_prof.used < g_prof.ev.size()) {
+    if (profile && g_prof.on && g_prof.calls++ % g_prof.every == 0 && g_prof.used < g_prof.ev.size()) {
         e0 = g_prof.ev[g_prof.used].first;
         e1 = g_prof.ev[g_prof.used].second;
         ++g_prof.used;
@@ -579,6 +583,13 @@ fov_status foveate_profile_begin(int32_t capacity) {
         g_prof.ev.emplace_back(a, b);
     }
     g_prof.on = true;
+    return FOV_OK;
+}
+
+fov_status foveate_profile_every(int32_t every) {
+    if (every < 1) return set_error(FOV_EINVAL, "every must be at least 1");
+    if (!g_prof.on) return set_error(FOV_EINVAL, "profiling was not started");
+    g_prof.every = every;
     return FOV_OK;
 }
 

@@ -32,6 +32,7 @@
 #include "forward.h"
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "conv.h"
 
@@ -650,13 +651,19 @@ fov_status launch_main(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, 
         }
         grid = std::max(1, std::min(a.nslots, Slot::occ_blocks * cus));
     }
-    if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return hip_error(e, "hipEventRecord");
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, stream, a, (const int32_t*)plan.radius,
-                       (const TC*)plan.weights, (const int32_t*)plan.order, (const FrameDesc*)a.table,
-                       (const int32_t*)a.prefix);
+    if (ev_start || ev_stop) {
+        // The dispatch itself stamps the events: no separate event packets (each would leave a
+        // gap of several microseconds between the kernels of the stream).
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, stream, ev_start, ev_stop, 0, a,
+                              (const int32_t*)plan.radius, (const TC*)plan.weights, (const int32_t*)plan.order,
+                              (const FrameDesc*)a.table, (const int32_t*)a.prefix);
+    } else {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, stream, a, (const int32_t*)plan.radius,
+                           (const TC*)plan.weights, (const int32_t*)plan.order, (const FrameDesc*)a.table,
+                           (const int32_t*)a.prefix);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "forward kernel launch");
-    if (ev_stop && (e = hipEventRecord(ev_stop, stream)) != hipSuccess) return hip_error(e, "hipEventRecord");
     return FOV_OK;
 }
 

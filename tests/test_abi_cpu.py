@@ -147,6 +147,12 @@ def test_tuning_force_validation():
     assert lib.foveate_tuning_force(None) == N.FOV_OK
 
 
+def test_profile_every_validation():
+    lib = N.lib()
+    assert lib.foveate_profile_every(2) == N.FOV_EINVAL  # no profile window on this thread
+    assert lib.foveate_profile_every(0) == N.FOV_EINVAL
+
+
 def test_tuning_file_roundtrip_and_errors(tmp_path):
     from paper_2012_08655_amd import _native as N
     lib = N.lib()

@@ -231,3 +231,18 @@ def test_u8_every_radius_phase(fov, orc, dev):
         assert err <= TOL_F32 * 255, (r, err)
         d = np.abs(y8.cpu().numpy().astype(np.int32) - orc.to_u8(ref).astype(np.int32))
         assert d.max() <= 1, r
+
+
+def test_profile_samples_one_call_in_every(fov, dev):
+    # profile_begin(n, every=k) times calls 0, k, 2k, ... of the window
+    x = torch.from_numpy(synth.uniform_frames((1, 64, 96), seed=5)).to(dev)
+    p = synth.params_dict(40.0, 30.0, 4.0, 0.1, 6.0)
+    fov.profile_begin(8, every=3)
+    for _ in range(7):
+        fov.forward(x, p, layout="CHW")
+    ms = fov.profile_end(8)
+    assert len(ms) == 3 and np.all(ms > 0)
+    fov.profile_begin(8)
+    for _ in range(5):
+        fov.forward(x, p, layout="CHW")
+    assert len(fov.profile_end(8)) == 5
