@@ -134,7 +134,7 @@ def _spin_until(lib, target):
         pass
 
 
-def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, seed=4, ring=8):
+def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, seed=4, ring=8, inflight=4):
     """Open-loop Poisson request traces (16 viewer sessions of mixed
     resolution, saccade + drift gaze) replayed twice on the same GPU: once
     through the continuous-batching server, once as plain per-frame
@@ -180,6 +180,7 @@ def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, s
         for mode in ("plain", "served"):
             torch.cuda.synchronize()
             done = np.zeros(n)
+            launched = np.zeros(n)
             batch = np.zeros(n, np.int32)
             if mode == "plain":
                 stamps = (ctypes.c_double * n)()
@@ -198,7 +199,7 @@ def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, s
                 done[:] = np.frombuffer(stamps, dtype=np.float64)
                 batch[:] = 1
             else:
-                srv = Server(hbm_budget_bytes=budget_mib << 20, max_batch_frames=max_batch, max_inflight_batches=2,
+                srv = Server(hbm_budget_bytes=budget_mib << 20, max_batch_frames=max_batch, max_inflight_batches=inflight,
                              max_requests=8192, max_fragments=max_frag, max_sigma=16.0, use_graph=use_graph)
                 tickets = np.zeros(n, np.uint64)
                 tk = ctypes.c_uint64()
@@ -211,6 +212,7 @@ def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, s
                                              ctypes.byref(tm)))
                     if done_flag.value:
                         done[i] = tm.t_done
+                        launched[i] = tm.t_launch
                         batch[i] = tm.batch_frames
                     return bool(done_flag.value)
 
@@ -234,12 +236,19 @@ def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, s
                          "max_ms": round(float(lat.max()), 4),
                          "mpix_s": round(float(pixels[measured].sum()) / span / 1e6, 1),
                          "mean_batch_frames": round(float(batch[measured].mean()), 3)}
+            if mode == "served":
+                # where the served latency goes: arrival -> launch (admission, batching, host
+                # launch work) and launch -> completion seen by the host
+                wait = (launched - (t0 + tr["t"]))[measured] * 1e3
+                run = (done - launched)[measured] * 1e3
+                res[mode]["to_launch_p50_p99_ms"] = [round(float(np.percentile(wait, q)), 4) for q in (50, 99)]
+                res[mode]["launch_to_done_p50_p99_ms"] = [round(float(np.percentile(run, q)), 4) for q in (50, 99)]
             print("bench: serving %s at %g fps: p50 %.3f ms, p99 %.3f ms" % (mode, rate, res[mode]["p50_ms"],
                                                                           res[mode]["p99_ms"]),
                   file=sys.stderr, flush=True)
         legs.append(res)
         del outs
-    return {"budget_mib": budget_mib, "max_batch_frames": max_batch, "max_inflight_batches": 2, "sessions": 16,
+    return {"budget_mib": budget_mib, "max_batch_frames": max_batch, "max_inflight_batches": inflight, "sessions": 16,
             "seconds_measured": seconds, "warmup_s": warm_s, "hip_graph": use_graph,
             "latency": "host-seen completion minus scheduled arrival",
             "plain": "one foveate_forward per frame on one stream at its arrival time",
@@ -379,6 +388,7 @@ def main():
     ap.add_argument("--serve-budget-mib", type=int, default=256)
     ap.add_argument("--serve-max-batch", type=int, default=16)
     ap.add_argument("--serve-graph", type=int, default=1, help="1: the server replays captured hipGraphs")
+    ap.add_argument("--serve-inflight", type=int, default=4, help="batches the server keeps in flight")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving traces")
     ap.add_argument("--no-extra", action="store_true", help="skip the batch and adjoint legs")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch configuration")
@@ -506,7 +516,7 @@ def main():
     if not args.no_serve:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
         result["serving"] = serving_leg(rates, args.serve_seconds, 0.5, args.serve_budget_mib, args.serve_max_batch,
-                                        use_graph=bool(args.serve_graph))
+                                        use_graph=bool(args.serve_graph), inflight=args.serve_inflight)
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(distinct[0], target_s=args.cpu_seconds)
