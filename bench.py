@@ -392,11 +392,18 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving traces")
     ap.add_argument("--no-extra", action="store_true", help="skip the batch and adjoint legs")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch configuration")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the forward/adjoint leg on the training batches (for a kernel trace) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain MB-sized device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, 5)
+        return
+    if args.adjoint_only:
+        import paper_2012_08655_amd as fov
+        fov.load()
+        print(json.dumps({"adjoint": adjoint_leg()}))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method needs no communication and this build "
