@@ -205,10 +205,15 @@ fov_status foveate_backward(const fov_tensor* grad_out, const fov_tensor* grad_i
  *                it (equal taps: the halo rows the two share are computed
  *                once); needs split 1.  By default it is on unless its taller
  *                tiles would let fewer workgroups share a CU.
+ *   chan_split : 1 = a fragment whose radius is at most 2/3 of the largest
+ *                radius of the call is one work item per channel (such items
+ *                come last in the queue and are latency bound: their channels
+ *                then run side by side); needs split 1 and at most 16
+ *                channels.  By default on for frames of several channels.
  *   time_us    : (output of foveate_autotune) median time of one call.
  */
 typedef struct {
-    int32_t split, strip_rows, persistent, merge;
+    int32_t split, strip_rows, persistent, merge, chan_split;
     float time_us;
 } fov_tuning;
 
@@ -221,8 +226,8 @@ typedef struct {
  * side, the bit length of the largest radius, the bit length of the fragment
  * count and the frame-count class (1, 2..16, more).  Later forward calls of
  * that class, from any thread, use the cached configuration; others use the
- * defaults (split 1, 64 strip rows, one workgroup per queue slot, merge as
- * described above).  Writes
+ * defaults (split 1, 64 strip rows, one workgroup per queue slot, merge and
+ * chan_split as described above).  Writes
  * the chosen configuration to *best (may be NULL).  Arguments and errors as
  * foveate_forward / foveate_forward_batch; `out` holds the foveated frames on
  * return.  Synchronises `stream`.
@@ -235,7 +240,8 @@ fov_status foveate_autotune_batch(const fov_tensor* ins, const fov_tensor* outs,
 /*
  * Force one configuration for the forward calls of the calling thread
  * (tests, experiments); NULL returns the thread to the cache and defaults.
- * FOV_EINVAL for values outside the sets above (or merge 1 with a split).  A forced configuration whose
+ * FOV_EINVAL for values outside the sets above (or merge or chan_split 1 with
+ * a split).  A forced configuration whose
  * LDS does not fit makes the forward call fail with FOV_ERANGE.
  */
 fov_status foveate_tuning_force(const fov_tuning* t);

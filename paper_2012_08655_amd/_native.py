@@ -44,7 +44,7 @@ class FovTiming(ctypes.Structure):
 
 class FovTuning(ctypes.Structure):
     _fields_ = [("split", ctypes.c_int32), ("strip_rows", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("merge", ctypes.c_int32), ("time_us", ctypes.c_float)]
+                ("merge", ctypes.c_int32), ("chan_split", ctypes.c_int32), ("time_us", ctypes.c_float)]
 
 
 # Every symbol declared in include/foveate.h, with (restype, argtypes).

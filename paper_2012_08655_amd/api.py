@@ -120,7 +120,7 @@ def forward_batch(frames, params, outs=None, layout: str = "HWC", out_dtype: tor
 
 def _tuning_dict(t: N.FovTuning) -> dict:
     return {"split": t.split, "strip_rows": t.strip_rows, "persistent": t.persistent, "merge": t.merge,
-            "time_us": t.time_us}
+            "chan_split": t.chan_split, "time_us": t.time_us}
 
 
 def autotune(x: torch.Tensor, params, out: torch.Tensor | None = None, layout: str = "NCHW",
@@ -154,13 +154,14 @@ def autotune_batch(frames, params, outs, layout: str = "HWC", reps: int = 5, str
     return _tuning_dict(t)
 
 
-def tuning_force(split: int | None = None, strip_rows: int = 64, persistent: int = 0, merge: int = 0):
+def tuning_force(split: int | None = None, strip_rows: int = 64, persistent: int = 0, merge: int = 0,
+                 chan_split: int = 0):
     """Force a launch configuration for this thread's forward calls
     (``split=None`` returns to the cache and defaults)."""
     if split is None:
         N.check(N.lib().foveate_tuning_force(None))
         return
-    t = N.FovTuning(int(split), int(strip_rows), int(persistent), int(merge), 0.0)
+    t = N.FovTuning(int(split), int(strip_rows), int(persistent), int(merge), int(chan_split), 0.0)
     N.check(N.lib().foveate_tuning_force(ctypes.byref(t)))
 
 

@@ -399,7 +399,13 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     a.r_cap = r_cap;
     a.strip_rows = sr;
     a.wstride = round_up(2 * r_cap + 1, 16);
-    a.nslots = queue_slots(a.nfrag << (2 * L), r_cap);
+    // Fragments of radius <= 2/3 of r_cap become one work item per channel (the latency-bound
+    // items at the end of the queue then run their channels side by side).
+    const bool chan = cfg.chan_split != 0 && L == 0 && cs.c > 1 && cs.c <= 16 && a.nfrag < (1 << kChanShift);
+    const int cs_rmax = chan ? (2 * r_cap) / 3 : -1;
+    a.cs_rmax = cs_rmax;
+    a.cmax = cs.c;
+    a.nslots = cs_rmax >= 0 ? queue_slots_by_channel(a.nfrag, r_cap, cs.c) : queue_slots(a.nfrag << (2 * L), r_cap);
     const size_t pbytes = (plan_bytes(a.nfrag, a.nslots, a.wstride, wsize) + 255) / 256 * 256;
     const bool upload = nf > kArgFrames;
     const size_t tbytes = frame_table_bytes(nf);

@@ -31,6 +31,12 @@ struct FwdLaunch {
     int32_t wstride;     // weights per fragment in the plan workspace (multiple of 16)
     int32_t from_args;   // 1: fr[]/kprefix[] hold the frames and the plan kernel
                          // copies them to table/prefix; 0: table/prefix were uploaded
+    int32_t cs_rmax;     // >= 0: a fragment with r <= cs_rmax becomes one work item per channel,
+                         // its channels in consecutive slots of one XCD after the rest of the
+                         // queue, so these short, latency-bound items run their channels side by
+                         // side and share that XCD's L2; -1: off.  Needs split_log2 = 0, fewer
+                         // than 2^26 fragments and cmax <= 16
+    int32_t cmax;        // largest channel count of the frames (with cs_rmax >= 0)
     int32_t merge;       // 1: a fragment at an even row whose sigma and the sigma of the fragment
                          // below both equal the cap becomes one work item with it (equal taps, so
                          // the halo rows they share are computed once); split_log2 must be 0
@@ -60,6 +66,14 @@ struct PlanBuffers {
 
 // Queue slots for nitems work items.
 int queue_slots(int nitems, int r_cap);
+// Queue slots when fragments may be split by channel (cs_rmax >= 0): room for one slot per
+// channel of every fragment and ring padding.
+int queue_slots_by_channel(int nfrag, int r_cap, int cmax);
+// Order entries of a per-channel work item (cs_rmax >= 0): bit 30 set, channel in bits 26-29,
+// fragment in bits 0-25.
+constexpr int32_t kChanItem = 1 << 30;
+constexpr int kChanShift = 26;
+constexpr int32_t kChanItemMask = (1 << kChanShift) - 1;
 size_t plan_bytes(int nfrag, int nslots, int wstride, int wsize);
 PlanBuffers carve_plan(void* ws, int nfrag, int nslots);
 

@@ -278,12 +278,12 @@ __device__ __forceinline__ bool narrow_to_tile(Frag& F, int L, int sub) {
 
 // Foveal fragment: copied (Appendix "Workload of the Block").
 template <typename TIn, typename TOut>
-__device__ __forceinline__ void copy_fragment(const Frag& F) {
+__device__ __forceinline__ void copy_fragment(const Frag& F, int c_lo, int c_hi) {
     const FrameDesc& d = *F.fd;
     const TIn* in = static_cast<const TIn*>(d.in);
     TOut* out = static_cast<TOut*>(d.out);
     const int wave = wave_id(), lane = threadIdx.x & 63;
-    for (int c = 0; c < d.c; ++c)
+    for (int c = c_lo; c < c_hi; ++c)
         for (int y = wave; y < F.bh; y += kThreads / 64)
             for (int x = lane; x < F.bw; x += 64) {
                 const TIn v = in[c * d.isc + (int64_t)(F.ya + y) * d.ish + (int64_t)(F.xa + x) * d.isw];
@@ -296,11 +296,11 @@ __device__ __forceinline__ void copy_fragment(const Frag& F) {
 // in flight while the current one is computed), horizontal pass into the
 // column-major intermediate, vertical pass into the output.
 template <typename TIn, typename TOut, typename TS, typename TC>
-__device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, int r, const Frag& F,
-                                                 const TC* __restrict__ wts, unsigned char* smem) {
+__device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, int r, const Frag& F, int c_lo,
+                                                 int c_hi, const TC* __restrict__ wts, unsigned char* smem) {
     const FrameDesc& d = *F.fd;
     if (r == 0) {
-        copy_fragment<TIn, TOut>(F);
+        copy_fragment<TIn, TOut>(F, c_lo, c_hi);
         return;
     }
     const int tid = threadIdx.x;
@@ -319,19 +319,19 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
     const TIn* in = static_cast<const TIn*>(d.in);
     TOut* out = static_cast<TOut*>(d.out);
     const int nst = (g.TH + SR - 1) / SR;
-    const int nunits = d.c * nst;
+    const int nunits = (c_hi - c_lo) * nst;  // (channel, strip) units, channels c_lo .. c_hi - 1
     Stager<TIn, TS> st;
     const int64_t span = (int64_t)(d.c - 1) * d.isc + (int64_t)(d.h - 1) * d.ish + (int64_t)(d.w - 1) * d.isw + 1;
     st.setup(F.xa - r - sh, TW, d.w, d.isw, d.ish, d.h, in, (uint32_t)span);
-    st.issue(in, F.ya - r, SR);
+    st.issue(in + c_lo * d.isc, F.ya - r, SR);
     st.commit(tile, TP);
     __syncthreads();
     for (int u = 0; u < nunits; ++u) {
-        const int c = u / nst, sidx = u - c * nst;
+        const int cu = u / nst, sidx = u - cu * nst, c = c_lo + cu;
         const int s0 = sidx * SR, rows = min(SR, g.TH - s0);
         if (u + 1 < nunits) {
             const int cn = (u + 1) / nst, sn = (u + 1) - cn * nst;
-            st.issue(in + cn * d.isc, F.ya - r + sn * SR, min(SR, g.TH - sn * SR));
+            st.issue(in + (c_lo + cn) * d.isc, F.ya - r + sn * SR, min(SR, g.TH - sn * SR));
         }
         // Horizontal pass.  Task t: lanes of a 16-lane group take 16
         // consecutive rows of one column group (conflict-free row reads).
@@ -390,10 +390,16 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
     const int nframes = a.hdr ? a.hdr[0] : a.nframes;
     const int L = a.split_log2;
     for (int q = blockIdx.x; q < nslots; q += gridDim.x) {
-        const int item = order[q];
+        int item = order[q];
         if (item < 0) {  // empty slot
             if (!PERSIST) break;
             continue;
+        }
+        int c_lo = 0, c_hi = 1 << 30;  // channels of this item (clipped to the frame's below)
+        if (a.cs_rmax >= 0 && (item & kChanItem)) {  // one channel of a fragment split by channel
+            c_lo = (item >> kChanShift) & 15;
+            c_hi = c_lo + 1;
+            item &= kChanItemMask;
         }
         const int gid = item >> (2 * L);
         const int rr = radius[gid];
@@ -407,7 +413,8 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
             if (!PERSIST) break;
             continue;
         }
-        process_fragment<TIn, TOut, TS, TC>(a, gid, r, F, wts, smem);
+        c_hi = min(c_hi, F.fd->c);
+        if (c_lo < c_hi) process_fragment<TIn, TOut, TS, TC>(a, gid, r, F, c_lo, c_hi, wts, smem);
         if (!PERSIST) break;
         __syncthreads();  // this fragment's LDS reads are done before the next one is staged
     }
@@ -530,13 +537,17 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
 __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t* __restrict__ okey, int n_arg,
                                                                   int L, int nrings, int nang, int nslots_arg,
                                                                   const int32_t* __restrict__ hdr,
-                                                                  int32_t* __restrict__ order) {
+                                                                  int32_t* __restrict__ order, int cs_rmax,
+                                                                  int cmax) {
     const int n = (hdr ? hdr[1] : n_arg) << (2 * L);  // work items
     const int nslots = hdr ? hdr[2] : nslots_arg;
     __shared__ int cells[kOrderCells];        // [ring][angle bin], ring 0 = largest radius
     __shared__ int ring_n[kOrderMaxRings];    // fragments per ring
     __shared__ int ring_base[kOrderMaxRings]; // first slot of each ring (multiple of 8)
-    __shared__ int total_slots;
+    __shared__ int chan_base[kOrderMaxRings]; // split rings: first slot of each after the queue
+    __shared__ int total_slots, total_extra;
+    // rings whose fragments (r <= cs_rmax) are split by channel: ring >= small0
+    const int small0 = (cs_rmax >= 0 && cmax > 1) ? max(nrings - 1 - cs_rmax, 0) : nrings;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ncell = nrings * nang;
     for (int i = tid; i < ncell; i += kOrderThreads) cells[i] = 0;
@@ -564,11 +575,11 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
     }
     __syncthreads();
     if (wave == 0) {
-        // ring bases: each ring takes 8 * ceil(n_ring / 8) slots
+        // ring bases: each ring takes 8 * ceil(n_ring / 8) slots (split rings go after the queue)
         int carry = 0;
         for (int r0 = 0; r0 < nrings; r0 += 64) {
             const int ring = r0 + lane;
-            const int v = ring < nrings ? round_up(ring_n[ring], kXcds) : 0;
+            const int v = ring < small0 ? round_up(ring_n[ring], kXcds) : 0;
             int incl = v;
             for (int off = 1; off < 64; off <<= 1) {
                 const int t = __shfl_up(incl, off, 64);
@@ -578,6 +589,20 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
             carry += __shfl(incl, 63, 64);
         }
         if (lane == 0) total_slots = carry;
+        // split rings after the queue, ring by ring: cmax slots per fragment
+        carry = 0;
+        for (int r0 = small0; r0 < nrings; r0 += 64) {
+            const int ring = r0 + lane;
+            const int v = ring < nrings ? round_up(ring_n[ring], kXcds) * cmax : 0;
+            int incl = v;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += t;
+            }
+            if (ring < nrings) chan_base[ring] = carry + incl - v;
+            carry += __shfl(incl, 63, 64);
+        }
+        if (lane == 0) total_extra = carry;
     }
     __syncthreads();
     for (int i = tid; i < n; i += kOrderThreads) {
@@ -588,18 +613,30 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
         const int m = ring_n[ring];
         const int arc = (j * kXcds) / m;                  // arc a holds ranks [ceil(a m/8), ceil((a+1) m/8))
         const int k = j - (arc * m + kXcds - 1) / kXcds;  // rank inside the arc
-        order[ring_base[ring] + kXcds * k + arc] = i;
+        if (ring < small0) {
+            order[ring_base[ring] + kXcds * k + arc] = i;
+        } else {  // one slot per channel, consecutive slots of the same XCD
+            const int e = total_slots + chan_base[ring] + kXcds * k * cmax + arc;
+            for (int ch = 0; ch < cmax; ++ch) order[e + kXcds * ch] = i | kChanItem | (ch << kChanShift);
+        }
     }
     // empty slots: arc a of a ring of m holds ceil((a+1)m/8) - ceil(a m/8) <= ceil(m/8) fragments
     for (int ring = wave; ring < nrings; ring += kOrderThreads / 64) {
         const int m = ring_n[ring], per = (m + kXcds - 1) / kXcds;
+        const bool split = ring >= small0;
         for (int t = lane; t < per * kXcds; t += 64) {
             const int arc = t % kXcds, k = t / kXcds;
             const int sz = ((arc + 1) * m + kXcds - 1) / kXcds - (arc * m + kXcds - 1) / kXcds;
-            if (k >= sz) order[ring_base[ring] + kXcds * k + arc] = -1;
+            if (k < sz) continue;
+            if (!split) {
+                order[ring_base[ring] + kXcds * k + arc] = -1;
+            } else {
+                const int e = total_slots + chan_base[ring] + kXcds * k * cmax + arc;
+                for (int ch = 0; ch < cmax; ++ch) order[e + kXcds * ch] = -1;
+            }
         }
     }
-    for (int q = total_slots + tid; q < nslots; q += kOrderThreads) order[q] = -1;
+    for (int q = total_slots + total_extra + tid; q < nslots; q += kOrderThreads) order[q] = -1;
 }
 
 // Device plan for foveate_plan(): sigma and radius only.
@@ -678,7 +715,7 @@ fov_status launch_typed(const FwdLaunch& a, size_t lds, const PlanBuffers& plan,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "plan kernel launch");
     hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.okey, a.nfrag,
-                       a.split_log2, nrings, nang, a.nslots, a.hdr, plan.order);
+                       a.split_log2, nrings, nang, a.nslots, a.hdr, plan.order, a.cs_rmax, a.cmax);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "order kernel launch");
     if (persist) return launch_main<TIn, TOut, TS, TC, true>(a, lds, plan, stream, lds_limit, cus, ev_start, ev_stop);
@@ -691,6 +728,8 @@ int compute_size(int in_dtype) { return in_dtype == FOV_F64 ? 8 : 4; }
 }  // namespace
 
 int queue_slots(int nitems, int r_cap) { return nitems + kXcds * order_rings(r_cap); }
+
+int queue_slots_by_channel(int nfrag, int r_cap, int cmax) { return cmax * queue_slots(nfrag, r_cap); }
 
 size_t plan_bytes(int nfrag, int nslots, int wstride, int wsize) {
     return 2 * align16((size_t)nfrag * 4) + align16((size_t)nslots * 4) + 256 + (size_t)nfrag * wstride * wsize;

@@ -57,6 +57,7 @@ struct LaunchCfg {
     int strip_rows = 64;
     bool persistent = false;
     int merge = -1;  // vertical pairs at the cap as one item: 1 on, 0 off, -1 on unless it lowers occupancy
+    int chan_split = -1;  // small radii one item per channel: 1 on, 0 off, -1 on (several channels)
 };
 
 // What a forward call launches: largest radius and fragment side, fragments.

@@ -153,6 +153,7 @@ FwdLaunch capacity_launch(const ServerImpl* s, const Slot& sl, PlanBuffers* plan
     FwdLaunch a;
     std::memset(&a, 0, sizeof(a));
     a.merge = merge ? 1 : 0;
+    a.cs_rmax = -1;  // whole fragments: batch sizes vary per replay
     a.nframes = s->cfg.max_batch_frames;
     a.nfrag = s->cfg.max_fragments;
     a.nslots = queue_slots(a.nfrag, s->r_cap);

@@ -3,7 +3,8 @@
 // and caches the fastest for the call's workload class.
 //
 // The choices (output tile split, strip height, dispatch mode, merged pairs of
-// capped fragments) change how fragments map onto workgroups, never the
+// capped fragments, per-channel items of small radii) change how fragments map
+// onto workgroups, never the
 // arithmetic of an output pixel, so the cache can be consulted freely: results
 // are the same bit for bit.
 #include <hip/hip_runtime.h>
@@ -73,6 +74,7 @@ LaunchCfg default_cfg() {
     c.strip_rows = choose_strip_rows();
     c.persistent = dispatch_persistent();
     c.merge = -1;
+    c.chan_split = -1;
     return c;
 }
 
@@ -80,7 +82,8 @@ bool valid_public(const fov_tuning& t) {
     return (t.split == 1 || t.split == 2 || t.split == 4) &&
            (t.strip_rows == 16 || t.strip_rows == 32 || t.strip_rows == 64) &&
            (t.persistent == 0 || t.persistent == 1) && (t.merge == 0 || t.merge == 1) &&
-           !(t.merge == 1 && t.split != 1);
+           (t.chan_split == 0 || t.chan_split == 1) && !(t.merge == 1 && t.split != 1) &&
+           !(t.chan_split == 1 && t.split != 1);
 }
 
 LaunchCfg from_public(const fov_tuning& t) {
@@ -89,6 +92,7 @@ LaunchCfg from_public(const fov_tuning& t) {
     c.strip_rows = t.strip_rows;
     c.persistent = t.persistent != 0;
     c.merge = t.merge;
+    c.chan_split = t.chan_split;
     return c;
 }
 
@@ -98,6 +102,7 @@ fov_tuning to_public(const LaunchCfg& c, float us) {
     t.strip_rows = c.strip_rows;
     t.persistent = c.persistent ? 1 : 0;
     t.merge = c.merge > 0 ? 1 : 0;
+    t.chan_split = c.chan_split != 0 ? 1 : 0;
     t.time_us = us;
     return t;
 }
@@ -120,14 +125,17 @@ std::vector<LaunchCfg> candidates(const DeviceInfo& dev, int in_dtype, const Cal
                 if (eff == prev) continue;
                 prev = eff;
                 if (forward_lds_bytes(in_dtype, cs.r_cap, tile, th, sr) + 64 > dev.lds_limit) continue;
-                for (bool persist : {false, true}) {
-                    LaunchCfg c;
-                    c.split_log2 = L;
-                    c.strip_rows = sr;
-                    c.persistent = persist;
-                    c.merge = merge;
-                    out.push_back(c);
-                }
+                for (bool persist : {false, true})
+                    for (int chan : {0, 1}) {
+                        if (chan && (L > 0 || cs.c < 2 || cs.c > 16)) continue;
+                        LaunchCfg c;
+                        c.split_log2 = L;
+                        c.strip_rows = sr;
+                        c.persistent = persist;
+                        c.merge = merge;
+                        c.chan_split = chan;
+                        out.push_back(c);
+                    }
             }
         }
     }
@@ -212,7 +220,7 @@ fov_status autotune_frames(const std::vector<FrameDesc>& frames, int in_dtype, i
     return FOV_OK;
 }
 
-constexpr const char* kTag = "fov-tune-v2";
+constexpr const char* kTag = "fov-tune-v3";
 
 }  // namespace
 
@@ -259,7 +267,9 @@ fov_status foveate_tuning_force(const fov_tuning* t) {
         g_forced_on = false;
         return FOV_OK;
     }
-    if (!valid_public(*t)) return set_error(FOV_EINVAL, "split must be 1, 2 or 4, strip_rows 16, 32 or 64, persistent 0 or 1");
+    if (!valid_public(*t))
+        return set_error(FOV_EINVAL, "split must be 1, 2 or 4, strip_rows 16, 32 or 64, persistent, merge and "
+                                     "chan_split 0 or 1 (merge and chan_split with split 1 only)");
     g_forced = from_public(*t);
     g_forced_on = true;
     return FOV_OK;
@@ -288,13 +298,13 @@ fov_status foveate_tuning_save(const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return set_error(FOV_EINVAL, std::string("cannot open ") + path + " for writing");
     std::fprintf(f, "# %s arch cus in_dtype out_dtype channels block r_bits frag_bits frames_class : split strip_rows "
-                    "persistent merge time_us\n", kTag);
+                    "persistent merge chan_split time_us\n", kTag);
     for (const auto& kv : copy) {
         const TuneKey& k = kv.first;
         const fov_tuning t = to_public(kv.second.cfg, kv.second.us);
-        std::fprintf(f, "%s %s %d %d %d %d %d %d %d %d : %d %d %d %d %.3f\n", kTag, k.arch.c_str(), k.cus, k.in_dtype,
-                     k.out_dtype, k.c, k.bmax, k.r_bits, k.frag_bits, k.frames_class, t.split, t.strip_rows,
-                     t.persistent, t.merge, (double)t.time_us);
+        std::fprintf(f, "%s %s %d %d %d %d %d %d %d %d : %d %d %d %d %d %.3f\n", kTag, k.arch.c_str(), k.cus,
+                     k.in_dtype, k.out_dtype, k.c, k.bmax, k.r_bits, k.frag_bits, k.frames_class, t.split,
+                     t.strip_rows, t.persistent, t.merge, t.chan_split, (double)t.time_us);
     }
     const bool ok = std::fclose(f) == 0;
     if (!ok) return set_error(FOV_EINVAL, std::string("error writing ") + path);
@@ -323,10 +333,11 @@ fov_status foveate_tuning_load(const char* path) {
         fov_tuning t;
         double us = 0.0;
         int used = 0;
-        const int got = std::sscanf(p, "%31s %63s %d %d %d %d %d %d %d %d : %d %d %d %d %lf %n", tag, arch, &k.cus,
-                                    &k.in_dtype, &k.out_dtype, &k.c, &k.bmax, &k.r_bits, &k.frag_bits,
-                                    &k.frames_class, &t.split, &t.strip_rows, &t.persistent, &t.merge, &us, &used);
-        if (got != 15 || std::strcmp(tag, kTag) != 0 || p[used] != '\0' || !valid_public(t) || k.cus < 1 ||
+        const int got = std::sscanf(p, "%31s %63s %d %d %d %d %d %d %d %d : %d %d %d %d %d %lf %n", tag, arch,
+                                    &k.cus, &k.in_dtype, &k.out_dtype, &k.c, &k.bmax, &k.r_bits, &k.frag_bits,
+                                    &k.frames_class, &t.split, &t.strip_rows, &t.persistent, &t.merge,
+                                    &t.chan_split, &us, &used);
+        if (got != 16 || std::strcmp(tag, kTag) != 0 || p[used] != '\0' || !valid_public(t) || k.cus < 1 ||
             k.in_dtype < 0 || k.in_dtype > 2 || k.out_dtype < 0 || k.out_dtype > 2 || k.c < 1 || k.bmax < 1 ||
             k.bmax > kMaxBlock || k.r_bits < 0 || k.r_bits > 31 || k.frag_bits < 0 || k.frag_bits > 62 ||
             k.frames_class < 0 || k.frames_class > 2 || !(us >= 0.0)) {

@@ -137,12 +137,13 @@ def test_backward_rejects_u8():
 def test_tuning_force_validation():
     from paper_2012_08655_amd import _native as N
     lib = N.lib()
-    for bad in ((3, 64, 0, 0), (1, 48, 0, 0), (1, 64, 2, 0), (0, 64, 0, 0), (1, 64, 0, 2), (2, 64, 0, 1)):
+    for bad in ((3, 64, 0, 0, 0), (1, 48, 0, 0, 0), (1, 64, 2, 0, 0), (0, 64, 0, 0, 0), (1, 64, 0, 2, 0),
+                (2, 64, 0, 1, 0), (1, 64, 0, 0, 2), (1, 64, 0, 0, -1), (2, 64, 0, 0, 1)):
         t = N.FovTuning(*bad, 0.0)
         assert lib.foveate_tuning_force(ctypes.byref(t)) == N.FOV_EINVAL
-    t = N.FovTuning(1, 64, 0, 1, 0.0)
+    t = N.FovTuning(1, 64, 0, 1, 1, 0.0)
     assert lib.foveate_tuning_force(ctypes.byref(t)) == N.FOV_OK
-    t = N.FovTuning(2, 32, 1, 0, 0.0)
+    t = N.FovTuning(2, 32, 1, 0, 0, 0.0)
     assert lib.foveate_tuning_force(ctypes.byref(t)) == N.FOV_OK
     assert lib.foveate_tuning_force(None) == N.FOV_OK
 
@@ -160,21 +161,22 @@ def test_tuning_file_roundtrip_and_errors(tmp_path):
     assert lib.foveate_tuning_clear() == N.FOV_OK
     good = tmp_path / "good.txt"
     good.write_text("# comment\n"
-                    "fov-tune-v2 gfx950:sramecc+:xnack- 256 0 0 3 32 6 11 0 : 2 32 1 0 87.500\n"
+                    "fov-tune-v3 gfx950:sramecc+:xnack- 256 0 0 3 32 6 11 0 : 2 32 1 0 0 87.500\n"
                     "\n"
-                    "fov-tune-v2 gfx950:sramecc+:xnack- 256 1 1 1 16 4 8 1 : 1 64 0 1 12.000\n")
+                    "fov-tune-v3 gfx950:sramecc+:xnack- 256 1 1 1 16 4 8 1 : 1 64 0 1 1 12.000\n")
     assert lib.foveate_tuning_load(str(good).encode()) == N.FOV_OK
     assert lib.foveate_tuning_count(ctypes.byref(n)) == N.FOV_OK and n.value == 2
     out = tmp_path / "out.txt"
     assert lib.foveate_tuning_save(str(out).encode()) == N.FOV_OK
     lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
     assert sorted(lines) == sorted(l for l in good.read_text().splitlines() if l.startswith("fov"))
-    for bad_line in ("fov-tune-v2 gfx950 256 0 0 3 32 6 11 0 : 3 32 1 0 1.0",      # split 3
-                     "fov-tune-v2 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 0",          # missing time
-                     "fov-tune-v1 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 0 1.0",      # wrong tag
-                     "fov-tune-v2 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 0 1.0 junk",  # trailing text
-                     "fov-tune-v2 gfx950 256 0 5 3 32 6 11 0 : 2 32 1 0 1.0",      # bad dtype
-                     "fov-tune-v2 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 1 1.0"):     # merge with a split
+    for bad_line in ("fov-tune-v3 gfx950 256 0 0 3 32 6 11 0 : 3 32 1 0 0 1.0",      # split 3
+                     "fov-tune-v3 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 0 0",          # missing time
+                     "fov-tune-v2 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 0 1.0",        # older format
+                     "fov-tune-v3 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 0 0 1.0 junk",  # trailing text
+                     "fov-tune-v3 gfx950 256 0 5 3 32 6 11 0 : 2 32 1 0 0 1.0",      # bad dtype
+                     "fov-tune-v3 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 1 0 1.0",      # merge with a split
+                     "fov-tune-v3 gfx950 256 0 0 3 32 6 11 0 : 2 32 1 0 1 1.0"):     # channel items with a split
         bad = tmp_path / "bad.txt"
         bad.write_text(good.read_text() + bad_line + "\n")
         assert lib.foveate_tuning_load(str(bad).encode()) == N.FOV_EINVAL

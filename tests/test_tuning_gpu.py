@@ -1,6 +1,7 @@
 """Launch tuning on the GPU: every configuration (output tile split, strip
-height, dispatch mode) gives bitwise the same output as the default launch,
-and the autotuner caches a configuration that later calls use."""
+height, dispatch mode, merged pairs, per-channel items) gives bitwise the same
+output as the default launch, and the autotuner caches a configuration that
+later calls use."""
 import itertools
 
 import numpy as np
@@ -11,21 +12,21 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = [(sp, sr, pe, mg) for sp, sr, pe, mg in itertools.product((1, 2, 4), (16, 32, 64), (0, 1), (0, 1))
-           if not (mg and sp != 1)]
+CONFIGS = [cfg for cfg in itertools.product((1, 2, 4), (16, 32, 64), (0, 1), (0, 1), (0, 1))
+           if not ((cfg[3] or cfg[4]) and cfg[0] != 1)]
 
 
 def run_all_configs(fov, fn):
     base = fn()
     torch.cuda.synchronize()
-    for split, sr, persist, merge in CONFIGS:
-        fov.tuning_force(split, sr, persist, merge)
+    for cfg in CONFIGS:
+        fov.tuning_force(*cfg)
         try:
             got = fn()
             torch.cuda.synchronize()
         finally:
             fov.tuning_force(None)
-        assert torch.equal(got, base), (split, sr, persist, merge)
+        assert torch.equal(got, base), cfg
     return base
 
 
