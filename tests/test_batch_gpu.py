@@ -89,3 +89,27 @@ def test_mixed_resolution_batch_of_64(fov, orc, dev):
         ref = orc.to_u8(orc.forward_points(frames[i].transpose(2, 0, 1).astype(np.float64), params[i], ys, xs))
         got = outs[i].cpu().numpy()[ys, xs, :]
         assert np.max(np.abs(got.astype(np.int32) - ref.astype(np.int32))) <= 1, (i, h, w)
+
+
+@pytest.mark.parametrize("chan_split", [0, 1])
+def test_batch_mixed_channel_counts(fov, orc, dev, chan_split):
+    # frames of 1, 2 and 4 channels in one launch: per-channel items of the small radii go up to
+    # the largest channel count, and frames with fewer channels skip the rest
+    rng = np.random.default_rng(31)
+    frames, params = [], []
+    for i, c in enumerate((1, 4, 2, 1, 4, 2, 4)):
+        h, w = int(rng.integers(20, 90)), int(rng.integers(20, 110))
+        frames.append(synth.uniform_frames((c, h, w), seed=40 + i))
+        params.append(synth.params_dict(rng.uniform(0, w - 1), rng.uniform(0, h - 1), 2.0, 0.2, 8.0, 16))
+    ins = [torch.from_numpy(f).to(dev) for f in frames]
+    fov.tuning_force(1, 64, 0, 0, chan_split)
+    try:
+        outs = fov.forward_batch(ins, params, layout="CHW")
+        alone = [fov.forward(t, p, layout="CHW") for t, p in zip(ins, params)]
+        torch.cuda.synchronize()
+    finally:
+        fov.tuning_force(None)
+    for i in range(len(frames)):
+        assert torch.equal(outs[i], alone[i]), i
+        ref = orc.forward(frames[i].astype(np.float64), params[i])
+        assert np.max(np.abs(outs[i].cpu().numpy() - ref)) <= 2e-5, i
