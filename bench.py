@@ -392,6 +392,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving traces")
     ap.add_argument("--no-extra", action="store_true", help="skip the batch and adjoint legs")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch configuration")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the 64-frame mixed batch leg (for a kernel trace) and exit")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the forward/adjoint leg on the training batches (for a kernel trace) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -399,6 +401,11 @@ def main():
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, 5)
+        return
+    if args.batch_only:
+        import paper_2012_08655_amd as fov
+        fov.load()
+        print(json.dumps({"batch": batch_leg()}))
         return
     if args.adjoint_only:
         import paper_2012_08655_amd as fov
