@@ -423,11 +423,12 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderMaxRings = 1024;
 constexpr int kOrderCells = 12288;
+constexpr int kOrderBins = 16;  // angle bins per ring: one 16-lane segment of a wave scans a ring
 constexpr int kXcds = 8;
 
 // Rings (distinct radii) and angle bins of the order histogram.
 int order_rings(int r_cap) { return std::min(r_cap + 1, kOrderMaxRings); }
-int order_angle_bins(int nrings) { return std::max(1, std::min(64, kOrderCells / nrings)); }
+int order_angle_bins(int nrings) { return std::max(1, std::min(kOrderBins, kOrderCells / nrings)); }
 
 __device__ __forceinline__ int angle_bin(const Frag& F, int nang) {
     const FrameParams& fp = F.fd->p;
@@ -557,21 +558,19 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
         if (key >= 0) atomicAdd(&cells[key], 1);  // -1: the lower fragment of a merged pair
     }
     __syncthreads();
-    // exclusive scan of the angle bins inside each ring (one wave per ring)
-    for (int ring = wave; ring < nrings; ring += kOrderThreads / 64) {
-        int carry = 0;
-        for (int b0 = 0; b0 < nang; b0 += 64) {
-            const int b = b0 + lane;
-            const int v = b < nang ? cells[ring * nang + b] : 0;
-            int incl = v;
-            for (int off = 1; off < 64; off <<= 1) {
-                const int t = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += t;
-            }
-            if (b < nang) cells[ring * nang + b] = carry + incl - v;
-            carry += __shfl(incl, 63, 64);
+    // exclusive scan of the angle bins inside each ring: 16-lane segments, four rings per wave
+    // (nang <= kOrderBins)
+    for (int ring = wave * 4 + (lane >> 4); ring < nrings; ring += kOrderThreads / 16) {
+        const int b = lane & 15;
+        const bool live = ring < nrings && b < nang;
+        const int v = live ? cells[ring * nang + b] : 0;
+        int incl = v;
+        for (int off = 1; off < 16; off <<= 1) {
+            const int t = __shfl_up(incl, off, 16);
+            if (b >= off) incl += t;
         }
-        if (lane == 0) ring_n[ring] = carry;
+        if (live) cells[ring * nang + b] = incl - v;
+        if (ring < nrings && b == 15) ring_n[ring] = incl;
     }
     __syncthreads();
     if (wave == 0) {
@@ -589,8 +588,9 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
             carry += __shfl(incl, 63, 64);
         }
         if (lane == 0) total_slots = carry;
+    } else if (wave == 1) {
         // split rings after the queue, ring by ring: cmax slots per fragment
-        carry = 0;
+        int carry = 0;
         for (int r0 = small0; r0 < nrings; r0 += 64) {
             const int ring = r0 + lane;
             const int v = ring < nrings ? round_up(ring_n[ring], kXcds) * cmax : 0;
@@ -620,20 +620,19 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
             for (int ch = 0; ch < cmax; ++ch) order[e + kXcds * ch] = i | kChanItem | (ch << kChanShift);
         }
     }
-    // empty slots: arc a of a ring of m holds ceil((a+1)m/8) - ceil(a m/8) <= ceil(m/8) fragments
-    for (int ring = wave; ring < nrings; ring += kOrderThreads / 64) {
+    // empty slots: arc a of a ring of m holds ceil((a+1)m/8) - ceil(a m/8) fragments, ceil(m/8)
+    // or one fewer, so each arc leaves at most its last slot empty (eight lanes per ring)
+    for (int ring = tid >> 3; ring < nrings; ring += kOrderThreads / kXcds) {
+        const int arc = tid & (kXcds - 1);
         const int m = ring_n[ring], per = (m + kXcds - 1) / kXcds;
-        const bool split = ring >= small0;
-        for (int t = lane; t < per * kXcds; t += 64) {
-            const int arc = t % kXcds, k = t / kXcds;
-            const int sz = ((arc + 1) * m + kXcds - 1) / kXcds - (arc * m + kXcds - 1) / kXcds;
-            if (k < sz) continue;
-            if (!split) {
-                order[ring_base[ring] + kXcds * k + arc] = -1;
-            } else {
-                const int e = total_slots + chan_base[ring] + kXcds * k * cmax + arc;
-                for (int ch = 0; ch < cmax; ++ch) order[e + kXcds * ch] = -1;
-            }
+        const int sz = ((arc + 1) * m + kXcds - 1) / kXcds - (arc * m + kXcds - 1) / kXcds;
+        if (sz == per) continue;
+        const int k = per - 1;
+        if (ring < small0) {
+            order[ring_base[ring] + kXcds * k + arc] = -1;
+        } else {
+            const int e = total_slots + chan_base[ring] + kXcds * k * cmax + arc;
+            for (int ch = 0; ch < cmax; ++ch) order[e + kXcds * ch] = -1;
         }
     }
     for (int q = total_slots + total_extra + tid; q < nslots; q += kOrderThreads) order[q] = -1;
