@@ -530,7 +530,10 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
 // angle around their frame's fixation and cut into eight contiguous arcs, arc
 // a going to slots congruent to a mod 8.  Each XCD thus works through one
 // angular sector ring by ring, with an equal share of every ring.  Rings are
-// padded to a multiple of 8 slots with empty slots (-1).
+// padded to a multiple of 8 slots with empty slots (-1).  With per-channel
+// items (cs_rmax >= 0) the rings of radius <= cs_rmax follow the rest of the
+// queue, each of their fragments in cmax consecutive slots of its arc's XCD
+// (one per channel).
 // One workgroup: LDS histogram over (ring, angle bin), scans, scatter; the
 // order inside one (ring, angle bin) cell is arbitrary and results do not
 // depend on it.
