@@ -109,12 +109,15 @@ fov_tuning to_public(const LaunchCfg& c, float us) {
 
 // Every configuration that fits the device's LDS for this call.  Strip heights
 // at or above the tallest padded tile behave alike; only the smallest such is
-// kept.  Splits stop at tiles of 8 pixels.
+// kept.  Splits stop at tiles of 8 pixels, and calls with enough fragments to
+// fill the chip several times over are not split (more halo work for nothing;
+// their work-item counts also make the single-workgroup order pass slow).
+constexpr int64_t kSplitMaxFragments = 4096;
 std::vector<LaunchCfg> candidates(const DeviceInfo& dev, int in_dtype, const CallShape& cs) {
     std::vector<LaunchCfg> out;
     for (int L = 0; L <= 2; ++L) {
         const int tile = (cs.bmax + (1 << L) - 1) >> L;
-        if (L > 0 && (tile < 8 || tile == cs.bmax)) break;
+        if (L > 0 && (tile < 8 || tile == cs.bmax || cs.nfrag >= kSplitMaxFragments)) break;
         for (int merge : {0, 1}) {
             if (merge && (L > 0 || cs.r_cap == 0)) continue;
             const int th = merge ? 2 * tile : tile;
