@@ -134,7 +134,8 @@ def _spin_until(lib, target):
         pass
 
 
-def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, seed=4, ring=8, inflight=4):
+def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, seed=4, ring=8, inflight=4,
+                shared_stream=False):
     """Open-loop Poisson request traces (16 viewer sessions of mixed
     resolution, saccade + drift gaze) replayed twice on the same GPU: once
     through the continuous-batching server, once as plain per-frame
@@ -200,7 +201,8 @@ def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, s
                 batch[:] = 1
             else:
                 srv = Server(hbm_budget_bytes=budget_mib << 20, max_batch_frames=max_batch, max_inflight_batches=inflight,
-                             max_requests=8192, max_fragments=max_frag, max_sigma=16.0, use_graph=use_graph)
+                             max_requests=8192, max_fragments=max_frag, max_sigma=16.0, use_graph=use_graph,
+                             shared_stream=shared_stream)
                 tickets = np.zeros(n, np.uint64)
                 tk = ctypes.c_uint64()
                 done_flag = ctypes.c_int32()
@@ -248,7 +250,8 @@ def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, s
                   file=sys.stderr, flush=True)
         legs.append(res)
         del outs
-    return {"budget_mib": budget_mib, "max_batch_frames": max_batch, "max_inflight_batches": inflight, "sessions": 16,
+    return {"budget_mib": budget_mib, "max_batch_frames": max_batch, "max_inflight_batches": inflight,
+            "shared_stream": shared_stream, "sessions": 16,
             "seconds_measured": seconds, "warmup_s": warm_s, "hip_graph": use_graph,
             "latency": "host-seen completion minus scheduled arrival",
             "plain": "one foveate_forward per frame on one stream at its arrival time",
@@ -389,6 +392,8 @@ def main():
     ap.add_argument("--serve-max-batch", type=int, default=16)
     ap.add_argument("--serve-graph", type=int, default=1, help="1: the server replays captured hipGraphs")
     ap.add_argument("--serve-inflight", type=int, default=4, help="batches the server keeps in flight")
+    ap.add_argument("--serve-shared-stream", type=int, default=0,
+                    help="1: in-flight batches queue on one stream instead of one stream each")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving traces")
     ap.add_argument("--no-extra", action="store_true", help="skip the batch and adjoint legs")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch configuration")
@@ -530,7 +535,8 @@ def main():
     if not args.no_serve:
         rates = [float(r) for r in args.serve_rates.split(",") if r]
         result["serving"] = serving_leg(rates, args.serve_seconds, 0.5, args.serve_budget_mib, args.serve_max_batch,
-                                        use_graph=bool(args.serve_graph), inflight=args.serve_inflight)
+                                        use_graph=bool(args.serve_graph), inflight=args.serve_inflight,
+                                        shared_stream=bool(args.serve_shared_stream))
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(distinct[0], target_s=args.cpu_seconds)

@@ -287,7 +287,9 @@ typedef struct {
     int32_t test_fake_device_us;  /* test hook: > 0 launches no kernels and completes each
                                      batch after this many microseconds (outputs untouched)     */
     int32_t test_fail_every;      /* test hook: every k-th batch completes with FOV_EHIP        */
-    int32_t reserved;             /* must be 0                                                  */
+    int32_t shared_stream;        /* 1: every in-flight batch queues on one stream (FIFO on the
+                                     device, as a plain per-frame loop); 0: one stream per batch,
+                                     in-flight batches run side by side                         */
 } fov_server_cfg;
 
 typedef struct {

@@ -34,7 +34,7 @@ class FovServerCfg(ctypes.Structure):
                 ("in_dtype", ctypes.c_int32), ("out_dtype", ctypes.c_int32), ("max_fragments", ctypes.c_int32),
                 ("max_block", ctypes.c_int32), ("max_sigma", ctypes.c_double), ("use_graph", ctypes.c_int32),
                 ("test_fake_device_us", ctypes.c_int32), ("test_fail_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("shared_stream", ctypes.c_int32)]
 
 
 class FovTiming(ctypes.Structure):

@@ -47,7 +47,8 @@ struct ServerImpl;
 struct Slot {
     ServerImpl* owner = nullptr;
     int index = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the slot's own stream (graph capture)
+    hipStream_t run = nullptr;     // the stream its batches run on: its own, or slot 0's when shared
     bool busy = false;
     std::vector<uint64_t> tickets;
     size_t bytes = 0;
@@ -267,13 +268,13 @@ fov_status launch_batch(ServerImpl* s, Slot& sl, const std::vector<FrameDesc>& f
         sl.main_params.gridDim = dim3((unsigned)hdr.nslots);
         hipError_t e = hipGraphExecKernelNodeSetParams(sl.exec, sl.main_node, &sl.main_params);
         if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams");
-        e = hipGraphLaunch(sl.exec, sl.stream);
+        e = hipGraphLaunch(sl.exec, sl.run);
         if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
         return FOV_OK;
     }
-    fov_status st = run_forward(frames, s->cfg.in_dtype, s->cfg.out_dtype, sl.stream);
+    fov_status st = run_forward(frames, s->cfg.in_dtype, s->cfg.out_dtype, sl.run);
     if (st != FOV_OK) return st;
-    hipError_t e = hipLaunchHostFunc(sl.stream, on_batch_done, &sl);
+    hipError_t e = hipLaunchHostFunc(sl.run, on_batch_done, &sl);
     if (e != hipSuccess) return hip_error(e, "hipLaunchHostFunc");
     return FOV_OK;
 }
@@ -355,8 +356,8 @@ fov_status validate_cfg(const fov_server_cfg& c) {
     if (c.max_fragments < 1 || c.max_fragments > (1 << 24)) return set_error(FOV_EINVAL, "max_fragments in 1..2^24");
     if (c.max_block < 1 || c.max_block > kMaxBlock) return set_error(FOV_EINVAL, "max_block in 1..64");
     if (!(c.max_sigma >= 0) || c.max_sigma > 1000) return set_error(FOV_EINVAL, "max_sigma in 0..1000");
-    if (c.test_fake_device_us < 0 || c.test_fail_every < 0 || c.reserved != 0)
-        return set_error(FOV_EINVAL, "bad test hook or reserved field");
+    if (c.test_fake_device_us < 0 || c.test_fail_every < 0 || (c.shared_stream != 0 && c.shared_stream != 1))
+        return set_error(FOV_EINVAL, "bad test hook or shared_stream");
     return FOV_OK;
 }
 
@@ -421,6 +422,7 @@ fov_status foveate_server_create(const fov_server_cfg* cfg, fov_server** out) {
                 release(s);
                 return st;
             }
+            sl.run = cfg->shared_stream ? s->slots[0].stream : sl.stream;
         }
     } else {
         s->fake = std::thread(fake_device_loop, s);

@@ -37,11 +37,12 @@ class Server:
     def __init__(self, hbm_budget_bytes: int, max_batch_frames: int = 64, max_inflight_batches: int = 2,
                  max_requests: int = 4096, in_dtype: str = "u8", out_dtype: str = "u8",
                  max_fragments: int = 200000, max_block: int = 32, max_sigma: float = 16.0,
-                 use_graph: bool = True, test_fake_device_us: int = 0, test_fail_every: int = 0):
+                 use_graph: bool = True, test_fake_device_us: int = 0, test_fail_every: int = 0,
+                 shared_stream: bool = False):
         cfg = N.FovServerCfg(int(hbm_budget_bytes), int(max_batch_frames), int(max_inflight_batches),
                              int(max_requests), _DT[in_dtype], _DT[out_dtype], int(max_fragments), int(max_block),
                              float(max_sigma), int(bool(use_graph)), int(test_fake_device_us),
-                             int(test_fail_every), 0)
+                             int(test_fail_every), int(bool(shared_stream)))
         h = ctypes.c_void_p()
         N.check(N.lib().foveate_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

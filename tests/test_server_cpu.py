@@ -4,6 +4,7 @@ The fake device runs no kernels: each batch "completes" a fixed delay after
 launch, so admission, batching, latency accounting and failure handling are
 exercised without a GPU.  Buffers are fake device addresses (never touched).
 """
+import ctypes
 import threading
 import time
 
@@ -163,3 +164,13 @@ def test_bad_config(field, value):
     with pytest.raises(N.FoveateError) as ei:
         server(**kw)
     assert ei.value.status == N.FOV_EINVAL
+
+
+def test_shared_stream_flag_validated():
+    cfg = N.FovServerCfg(10 ** 9, 4, 2, 64, N.FOV_F32, N.FOV_F32, 1000, 32, 4.0, 0, 3000, 0, 2)
+    h = ctypes.c_void_p()
+    assert N.lib().foveate_server_create(ctypes.byref(cfg), ctypes.byref(h)) == N.FOV_EINVAL
+    with server(shared_stream=True, max_inflight_batches=3) as s:
+        ts = [s.submit_desc(*desc(i), P) for i in range(10)]
+        s.drain()
+        assert all(s.poll(t)[0] for t in ts)

@@ -55,15 +55,17 @@ def test_served_equals_plain(fov, dev, use_graph):
     assert sizes[0] == 1 and max(sizes[1:]) > 1  # the blocker alone, later frames batched
 
 
-def test_served_overlapping_streams_equal_plain(fov, dev):
-    # two streams, arrivals spread out: batches overlap on the device; results unchanged
+@pytest.mark.parametrize("shared", [False, True])
+def test_served_overlapping_streams_equal_plain(fov, dev, shared):
+    # two batches in flight, arrivals spread out: on two streams they overlap on the device, on
+    # one shared stream they queue; results unchanged
     items = frames_and_params(30, seed=11)
     ins = [torch.from_numpy(f).to(dev) for f, _ in items]
     outs = [torch.empty_like(t) for t in ins]
     plain = [fov.forward(t, p, layout="HWC") for t, (_, p) in zip(ins, items)]
     torch.cuda.synchronize()
     with Server(hbm_budget_bytes=256 << 20, max_batch_frames=8, max_inflight_batches=2, max_fragments=20000,
-                max_sigma=16.0, use_graph=True) as s:
+                max_sigma=16.0, use_graph=True, shared_stream=shared) as s:
         tickets = []
         for k, (t, o, (_, p)) in enumerate(zip(ins, outs, items)):
             tickets.append(s.submit(t, o, p))
