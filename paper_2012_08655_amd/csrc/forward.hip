@@ -20,15 +20,18 @@
 //     thread computes 8 (horizontal) or 4 (vertical) outputs and slides the
 //     filter window through registers (the register reuse of Appendix "Data
 //     Reuse"); the weights are read with scalar loads and used as SGPR
-//     operands of the FMAs.  For 8-bit input the horizontal pass adds the
-//     two samples that share a weight (the taps are symmetric) exactly in
-//     packed fp16 before the FP32 multiply-add.  A fragment with r = 0 is
-//     copied.
+//     operands of the FMAs.  For 8-bit input the horizontal pass of a
+//     fragment up to 32 wide with r <= 48 runs on the matrix cores (fp16
+//     samples times a Toeplitz matrix of hi/lo-split taps, fp32
+//     accumulation); beyond that it adds the two samples that share a weight
+//     (the taps are symmetric) exactly in packed fp16 before the FP32
+//     multiply-add.  A fragment with r = 0 is copied.
 //
 // Every output sums its taps in the same order (k = -r .. r; for 8-bit input
-// the horizontal pass goes k = 0, then the pairs +-1 .. +-r) whatever the
-// strip height, output tile split or dispatch mode, so results do not depend
-// on tuning choices.
+// the horizontal pass goes by 32-column chunks anchored at the fragment's
+// left edge, or k = 0, then the pairs +-1 .. +-r) whatever the strip height,
+// output tile split or dispatch mode, so results do not depend on tuning
+// choices.
 #include "forward.h"
 
 #include <hip/hip_runtime.h>
@@ -257,6 +260,84 @@ struct Stager<uint8_t, _Float16> {
     }
 };
 
+// ---- horizontal pass on the matrix cores (8-bit input) -------------------------------------------
+// The horizontal pass of a fragment is a banded product: rows of the staged tile (exact fp16 integers
+// 0..255) times the Toeplitz matrix T[c][x] = w_{c-x}, c - x in [0, 2r].  It runs as
+// v_mfma_f32_16x16x32_f16: 16 tile rows x 32 tile columns (A) times 32 x 16 of T (B) per instruction,
+// accumulated in fp32.  An fp32 tap w is split into fp16 w_hi = fp16(w) and w_lo = fp16((w - w_hi) 2^11);
+// the two products go to separate accumulators and the result is C_hi + 2^-11 C_lo, so the taps keep
+// about 22 significant bits and every product is exact (8-bit sample times an 11-bit significand).
+//
+// Column chunks of 32 are anchored at the whole fragment's left edge minus r (not at a split tile's),
+// and rows are independent, so an output's sum is grouped the same way under every strip height,
+// output tile split and dispatch mode.
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaRmax = 48;    // radii taken by the matrix-core pass (at most 4 column chunks)
+constexpr int kMfmaChunks = 4;   // 32-column chunks per 16-column output tile: (31 + 2r) / 32 + 1 <= 4
+constexpr int kMfmaCols = 32;    // output columns of a fragment (two 16-column tiles)
+constexpr int kTapTabLead = 32;  // table entry k + kTapTabLead packs taps (w_k, w_{k+1}), zero off [0, 2r]
+constexpr int kTapTabN = 32 * kMfmaChunks + kTapTabLead;
+constexpr float kTapLoScale = 2048.0f;
+
+// Staged columns for the matrix-core pass: whole chunks covering the last output tile's band.
+__host__ __device__ inline int mfma_tile_cols(int r) { return 32 * ((kMfmaCols - 1 + 2 * r) / 32 + 1); }
+// Row pitch in halves, = 8 (mod 64): the 16-byte A-operand reads of eight consecutive rows cover the
+// 32 banks once.
+__host__ __device__ inline int mfma_tile_pitch(int r) { return round_up(mfma_tile_cols(r) - 8, 64) + 8; }
+
+struct MfmaLayout {
+    int TP, IP, rows;       // tile pitch (halves), intermediate column pitch (floats), tile rows
+    size_t inter_off, tab_off, bytes;
+};
+
+// LDS of the matrix-core path for a fragment of TH staged rows and strips of SR rows.
+__host__ __device__ inline MfmaLayout mfma_layout(int r, int TH, int SR) {
+    MfmaLayout m;
+    m.TP = mfma_tile_pitch(r);
+    m.rows = round_up(SR, 16);
+    m.IP = inter_pitch(round_up(TH, 16), 4);
+    m.inter_off = kTileLead + align16((size_t)m.rows * m.TP * 2);
+    m.tab_off = m.inter_off + (size_t)kMfmaCols * m.IP * 4;
+    m.bytes = m.tab_off + 2 * kTapTabN * 4;
+    return m;
+}
+
+__device__ __forceinline__ uint32_t pack_h2(_Float16 a, _Float16 b) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+// Tap tables: hi[k + lead] = (w_hi[k], w_hi[k+1]), lo likewise with the scaled low parts.
+__device__ __forceinline__ void build_tap_tables(uint32_t* hi, uint32_t* lo, const float* __restrict__ w, int r) {
+    for (int e = threadIdx.x; e < kTapTabN; e += kThreads) {
+        const int k = e - kTapTabLead;
+        const float w0 = (k >= 0 && k <= 2 * r) ? w[k] : 0.0f;
+        const float w1 = (k + 1 >= 0 && k + 1 <= 2 * r) ? w[k + 1] : 0.0f;
+        const _Float16 h0 = (_Float16)w0, h1 = (_Float16)w1;
+        hi[e] = pack_h2(h0, h1);
+        lo[e] = pack_h2((_Float16)((w0 - (float)h0) * kTapLoScale), (_Float16)((w1 - (float)h1) * kTapLoScale));
+    }
+}
+
+// B operand of chunk kc for output tile n: lane (m = lane % 16, g = lane / 16) holds
+// T[32 kc + 8 g + j][16 n + m] = w_{32 kc + 8 g + j - 16 n - m}, j = 0..7.
+__device__ __forceinline__ h8v tap_operand(const uint32_t* tab, int kc, int n, int lane) {
+    const int k0 = 32 * kc + 8 * (lane >> 4) - 16 * n - (lane & 15) + kTapTabLead;  // 1 .. 152
+    uint32_t u[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = tab[k0 + 2 * i];
+    return __builtin_bit_cast(h8v, u);
+}
+
+// Whole-fragment column extent (a split tile narrows F.xa / F.bw; the chunk anchor stays put).
+__device__ __forceinline__ void fragment_cols(const Frag& F, int& xa, int& bw) {
+    const FrameParams& fp = F.fd->p;
+    const int X0 = fp.origin_x + F.bx * fp.block;
+    xa = max(X0, 0);
+    bw = min(X0 + fp.block, F.fd->w) - xa;
+}
+
 // ---- fragments of a launch ---------------------------------------------------------------------
 // Narrow a fragment to output tile `sub` of its L-level split: tiles of
 // T = ceil(B / 2^L) pixels a side, row-major, clipped to the fragment and the
@@ -295,37 +376,86 @@ __device__ __forceinline__ void copy_fragment(const Frag& F, int c_lo, int c_hi)
 // One fragment: stage its padded tile strip by strip (the next strip's loads
 // in flight while the current one is computed), horizontal pass into the
 // column-major intermediate, vertical pass into the output.
-template <typename TIn, typename TOut, typename TS, typename TC>
-__device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, int r, const Frag& F, int c_lo,
-                                                 int c_hi, const TC* __restrict__ wts, unsigned char* smem) {
+// MF: the matrix-core horizontal pass (8-bit input, fragments up to 32 wide, r <= 48).  The two
+// paths are separate instances so that neither holds the other's registers.
+template <typename TIn, typename TOut, typename TS, typename TC, bool MF>
+__device__ __forceinline__ void fragment_passes(const FwdLaunch& a, int gid, int r, const Frag& F, int c_lo,
+                                                int c_hi, const TC* __restrict__ wts, unsigned char* smem) {
     const FrameDesc& d = *F.fd;
-    if (r == 0) {
-        copy_fragment<TIn, TOut>(F, c_lo, c_hi);
-        return;
-    }
     const int tid = threadIdx.x;
     const TC* __restrict__ w = wts + (size_t)gid * a.wstride;
     const Geom g = geom(r, F.bw, F.bh);
-    const int SR = min(min(a.strip_rows, kStripMax), g.TH);
-    // 8-bit input: the symmetric horizontal pass wants each output's centre on a 4-sample group,
-    // so the tile starts sh = (-r) mod 4 columns further left.
+    // 8-bit input without MF: the symmetric pass, which wants each output's centre on a 4-sample
+    // group, so its tile starts sh = (-r) mod 4 columns further left.
     constexpr bool kSym = std::is_same<TS, _Float16>::value;
-    const int sh = kSym ? ((-r) & 3) : 0;
-    const int TW = g.TW + sh;
-    const int TP = tile_pitch(TW, sizeof(TS));
-    const int IP = inter_pitch(g.TH, sizeof(TC));
+    static_assert(!MF || kSym, "the matrix-core pass takes 8-bit input staged as fp16");
+    int SR = min(min(a.strip_rows, kStripMax), g.TH);
+    // matrix-core strips are whole 16-row tiles (or the whole tile), so the rows a strip computes
+    // past its end stay below round_up(TH, 16)
+    if (MF && SR < g.TH) SR = max(16, SR & ~15);
+    int xa_f = F.xa, bw_f = F.bw;
+    if constexpr (MF) fragment_cols(F, xa_f, bw_f);
+    const int sh = (kSym && !MF) ? ((-r) & 3) : 0;
+    MfmaLayout ml{};
+    int TW, TP, IP;
+    size_t inter_off;
+    if constexpr (MF) {
+        ml = mfma_layout(r, g.TH, SR);
+        TW = mfma_tile_cols(r);
+        TP = ml.TP;
+        IP = ml.IP;
+        inter_off = ml.inter_off;
+    } else {
+        TW = g.TW + sh;
+        TP = tile_pitch(TW, sizeof(TS));
+        IP = inter_pitch(g.TH, sizeof(TC));
+        inter_off = kTileLead + align16((size_t)SR * TP * sizeof(TS));
+    }
+    const int xoff = F.xa - xa_f;  // this tile's first column in the intermediate
     TS* tile = reinterpret_cast<TS*>(smem + kTileLead);
-    TC* inter = reinterpret_cast<TC*>(smem + kTileLead + align16((size_t)SR * TP * sizeof(TS)));  // [column][row]
+    TC* inter = reinterpret_cast<TC*>(smem + inter_off);  // [column][row]
     const TIn* in = static_cast<const TIn*>(d.in);
     TOut* out = static_cast<TOut*>(d.out);
     const int nst = (g.TH + SR - 1) / SR;
     const int nunits = (c_hi - c_lo) * nst;  // (channel, strip) units, channels c_lo .. c_hi - 1
     Stager<TIn, TS> st;
     const int64_t span = (int64_t)(d.c - 1) * d.isc + (int64_t)(d.h - 1) * d.ish + (int64_t)(d.w - 1) * d.isw + 1;
-    st.setup(F.xa - r - sh, TW, d.w, d.isw, d.ish, d.h, in, (uint32_t)span);
+    st.setup(xa_f - r - sh, TW, d.w, d.isw, d.ish, d.h, in, (uint32_t)span);
     st.issue(in + c_lo * d.isc, F.ya - r, SR);
+    // matrix-core pass: this wave's output tile n and its chunks; tap tables into LDS
+    const int lane = tid & 63, wave = wave_id();
+    int mn = 0, mrt0 = 0, mrts = 1, mnk = 0;
+    h8v bh[kMfmaChunks], bl[kMfmaChunks];
+    uint32_t* tab_hi = reinterpret_cast<uint32_t*>(smem + ml.tab_off);
+    uint32_t* tab_lo = tab_hi + kTapTabN;
+    if constexpr (MF) {
+        {
+            build_tap_tables(tab_hi, tab_lo, reinterpret_cast<const float*>(w), r);
+            const int n_lo = xoff >> 4, n_hi = (xoff + F.bw - 1) >> 4;
+            if (n_hi > n_lo) {  // two output tiles: waves 0, 2 take the left one, 1, 3 the right
+                mn = n_lo + (wave & 1);
+                mrt0 = wave >> 1;
+                mrts = 2;
+            } else {
+                mn = n_lo;
+                mrt0 = wave;
+                mrts = 4;
+            }
+            mnk = (16 * mn + 15 + 2 * r) / 32 + 1;
+        }
+    }
     st.commit(tile, TP);
     __syncthreads();
+    if constexpr (MF) {
+        {
+#pragma unroll
+            for (int i = 0; i < kMfmaChunks; ++i)
+                if (i < mnk) {
+                    bh[i] = tap_operand(tab_hi, i, mn, lane);
+                    bl[i] = tap_operand(tab_lo, i, mn, lane);
+                }
+        }
+    }
     for (int u = 0; u < nunits; ++u) {
         const int cu = u / nst, sidx = u - cu * nst, c = c_lo + cu;
         const int s0 = sidx * SR, rows = min(SR, g.TH - s0);
@@ -333,21 +463,49 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
             const int cn = (u + 1) / nst, sn = (u + 1) - cn * nst;
             st.issue(in + (c_lo + cn) * d.isc, F.ya - r + sn * SR, min(SR, g.TH - sn * SR));
         }
-        // Horizontal pass.  Task t: lanes of a 16-lane group take 16
-        // consecutive rows of one column group (conflict-free row reads).
-        const int ntask = round_up(rows, 16) * g.G;
-        for (int t = tid; t < ntask; t += kThreads) {
-            const int blk = t >> 4, gi = blk % g.G;
-            const int ty = ((blk / g.G) << 4) | (t & 15), x0 = gi * kPH;
-            if (ty >= rows) continue;
-            TC acc[kPH];
+        if constexpr (MF) {
+            {
+                // Row tile rt: tile rows 16 rt .. 16 rt + 15 (rows past the strip are computed from
+                // stale or unset LDS and land in intermediate rows that no tap reads).
+                const int nrt = (rows + 15) >> 4;
+                const _Float16* arow = reinterpret_cast<const _Float16*>(tile) + (lane & 15) * TP + 8 * (lane >> 4);
+                for (int rt = mrt0; rt < nrt; rt += mrts) {
+                    f4v ch = {0.0f, 0.0f, 0.0f, 0.0f}, cl = {0.0f, 0.0f, 0.0f, 0.0f};
+                    const _Float16* ar = arow + 16 * rt * TP;
 #pragma unroll
-            for (int p = 0; p < kPH; ++p) acc[p] = 0;
-            if constexpr (kSym) hconv_sym(acc, tile + ty * TP + x0 + r + sh, r, w + r);
-            else hconv(acc, tile + ty * TP + x0, g.N, w);
-            TC* dst = inter + x0 * IP + s0 + ty;
+                    for (int i = 0; i < kMfmaChunks; ++i)
+                        if (i < mnk) {
+                            const h8v av = *reinterpret_cast<const h8v*>(ar + 32 * i);
+                            ch = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bh[i], ch, 0, 0, 0);
+                            cl = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bl[i], cl, 0, 0, 0);
+                        }
+                    // lane holds rows 16 rt + 4 (lane / 16) + 0..3 of column 16 mn + lane % 16
+                    float4 o;
+                    o.x = fmaf(cl[0], 1.0f / kTapLoScale, ch[0]);
+                    o.y = fmaf(cl[1], 1.0f / kTapLoScale, ch[1]);
+                    o.z = fmaf(cl[2], 1.0f / kTapLoScale, ch[2]);
+                    o.w = fmaf(cl[3], 1.0f / kTapLoScale, ch[3]);
+                    *reinterpret_cast<float4*>(reinterpret_cast<float*>(inter) + (16 * mn + (lane & 15)) * IP + s0 +
+                                               16 * rt + 4 * (lane >> 4)) = o;
+                }
+            }
+        } else {
+            // Horizontal pass.  Task t: lanes of a 16-lane group take 16
+            // consecutive rows of one column group (conflict-free row reads).
+            const int ntask = round_up(rows, 16) * g.G;
+            for (int t = tid; t < ntask; t += kThreads) {
+                const int blk = t >> 4, gi = blk % g.G;
+                const int ty = ((blk / g.G) << 4) | (t & 15), x0 = gi * kPH;
+                if (ty >= rows) continue;
+                TC acc[kPH];
 #pragma unroll
-            for (int p = 0; p < kPH; ++p) dst[p * IP] = acc[p];
+                for (int p = 0; p < kPH; ++p) acc[p] = 0;
+                if constexpr (kSym) hconv_sym(acc, tile + ty * TP + x0 + r + sh, r, w + r);
+                else hconv(acc, tile + ty * TP + x0, g.N, w);
+                TC* dst = inter + x0 * IP + s0 + ty;
+#pragma unroll
+                for (int p = 0; p < kPH; ++p) dst[p * IP] = acc[p];
+            }
         }
         __syncthreads();  // the tile is free; the channel's intermediate may be complete
         if (sidx == nst - 1) {
@@ -358,7 +516,7 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
                 TC acc[kPV];
 #pragma unroll
                 for (int p = 0; p < kPV; ++p) acc[p] = 0;
-                vconv(acc, inter + x * IP + y0, g.N, w);
+                vconv(acc, inter + (x + xoff) * IP + y0, g.N, w);
                 TOut* o = oc + (int64_t)(F.xa + x) * d.osw;
 #pragma unroll
                 for (int p = 0; p < kPV; ++p)
@@ -370,6 +528,22 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
             __syncthreads();  // next strip staged; every thread is past the previous vertical pass
         }
     }
+}
+
+template <typename TIn, typename TOut, typename TS, typename TC>
+__device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, int r, const Frag& F, int c_lo,
+                                                 int c_hi, const TC* __restrict__ wts, unsigned char* smem) {
+    if (r == 0) {
+        copy_fragment<TIn, TOut>(F, c_lo, c_hi);
+        return;
+    }
+    if constexpr (std::is_same<TS, _Float16>::value) {
+        if (F.fd->p.block <= kMfmaCols && r <= kMfmaRmax) {
+            fragment_passes<TIn, TOut, TS, TC, true>(a, gid, r, F, c_lo, c_hi, wts, smem);
+            return;
+        }
+    }
+    fragment_passes<TIn, TOut, TS, TC, false>(a, gid, r, F, c_lo, c_hi, wts, smem);
 }
 
 // Work items are taken from the queue (by decreasing radius, so the costliest
@@ -759,7 +933,15 @@ size_t forward_lds_bytes(int in_dtype, int r_cap, int tile_w, int tile_h, int st
     const int es = stage_size(in_dtype), ec = compute_size(in_dtype);
     // 8-bit input: (-r) mod 4 leading columns; 2r + ((-r) mod 4) never decreases with r, so r_cap sizes them
     const int TW = g.TW + (in_dtype == FOV_U8 ? ((-r_cap) & 3) : 0);
-    return kTileLead + align16((size_t)rows * tile_pitch(TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec + 64;
+    size_t bytes = kTileLead + align16((size_t)rows * tile_pitch(TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec;
+    if (in_dtype == FOV_U8 && r_cap > 0) {
+        // fragments with r <= 48 (up to 32 columns wide) take the matrix-core pass
+        const int rm = std::min(r_cap, kMfmaRmax);
+        const Geom gm = geom(rm, tile_w, tile_h);
+        const int srm = std::min(std::min(strip_rows, kStripMax), gm.TH);
+        bytes = std::max(bytes, mfma_layout(rm, gm.TH, srm).bytes);
+    }
+    return bytes + 64;
 }
 
 fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,
