@@ -20,18 +20,15 @@
 //     thread computes 8 (horizontal) or 4 (vertical) outputs and slides the
 //     filter window through registers (the register reuse of Appendix "Data
 //     Reuse"); the weights are read with scalar loads and used as SGPR
-//     operands of the FMAs.  For 8-bit input the horizontal pass of a
-//     fragment up to 32 wide with r <= 48 runs on the matrix cores (fp16
-//     samples times a Toeplitz matrix of hi/lo-split taps, fp32
-//     accumulation); beyond that it adds the two samples that share a weight
-//     (the taps are symmetric) exactly in packed fp16 before the FP32
-//     multiply-add.  A fragment with r = 0 is copied.
+//     operands of the FMAs.  For 8-bit input the horizontal pass adds the
+//     two samples that share a weight (the taps are symmetric) exactly in
+//     packed fp16 before the FP32 multiply-add.  A fragment with r = 0 is
+//     copied.
 //
 // Every output sums its taps in the same order (k = -r .. r; for 8-bit input
-// the horizontal pass goes by 32-column chunks anchored at the fragment's
-// left edge, or k = 0, then the pairs +-1 .. +-r) whatever the strip height,
-// output tile split or dispatch mode, so results do not depend on tuning
-// choices.
+// the horizontal pass goes k = 0, then the pairs +-1 .. +-r) whatever the
+// strip height, output tile split or dispatch mode, so results do not depend
+// on tuning choices.
 #include "forward.h"
 
 #include <hip/hip_runtime.h>
@@ -160,19 +157,13 @@ struct Stager {
 // buffer loads over the frame (a descriptor covering its bytes): each lane's
 // two column offsets are fixed for the fragment and a row's offset is a
 // wave-uniform scalar, so no per-row address arithmetic runs on the vector
-// unit.  When a lane's two pixels are adjacent (no clamping), the row pitch is
-// a multiple of 4 bytes and the strip's reads end inside the frame, each lane
-// reads its pair with one 4-byte-aligned 8-byte load and picks the two bytes
-// with a byte permute (one load instruction per row instead of two).
+// unit; reads past the descriptor's range would return 0.
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ half2_t packed_bytes_to_half2(uint32_t b01) {  // b01 = b0 | b1 << 16
-    const half2_t bias = {(_Float16)1024.0f, (_Float16)1024.0f};
-    return __builtin_bit_cast(half2_t, b01 | 0x64006400u) - bias;
-}
-
 __device__ __forceinline__ half2_t bytes_to_half2(uint32_t b0, uint32_t b1) {
-    return packed_bytes_to_half2((b1 << 16) | b0);
+    const half2_t bias = {(_Float16)1024.0f, (_Float16)1024.0f};
+    const uint32_t bits = (b1 << 16) | b0 | 0x64006400u;
+    return __builtin_bit_cast(half2_t, bits) - bias;
 }
 
 // Raw buffer descriptor (dword 3 as gfx9 expects for untyped access).
@@ -184,54 +175,34 @@ __device__ __forceinline__ uint32_t load_byte(__amdgpu_buffer_rsrc_t rsrc, uint3
 
 template <>
 struct Stager<uint8_t, _Float16> {
-    uint32_t b0[kRowsPerWave], b1[kRowsPerWave];  // two bytes, or (wide) the 8 bytes holding them
+    uint32_t b0[kRowsPerWave], b1[kRowsPerWave];
     uint32_t c0, c1;
-    bool cv, pair;
-    bool wide;              // this strip: one 8-byte load per lane and row
-    uint32_t wvoff, wsel;   // its aligned column offset and byte selector
+    bool cv;
     __amdgpu_buffer_rsrc_t rsrc;
     const uint8_t* base;
     uint32_t poff, ish;
-    uint32_t isw, span;
+    uint32_t isw;
     int y0, rows, h, w, x_first, TW;
 
     // base: the frame's first byte; span: bytes from base to its last byte + 1 (< 2^31)
     __device__ __forceinline__ void setup(int x_first_, int TW_, int w_, int64_t isw_, int64_t ish_, int h_,
-                                          const uint8_t* base_, uint32_t span_) {
+                                          const uint8_t* base_, uint32_t span) {
         x_first = x_first_; TW = TW_; w = w_; isw = (uint32_t)isw_; ish = (uint32_t)ish_; h = h_;
         base = base_;
-        span = span_;
-        rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base_), 0, (int)span_, kBufferWord3);
+        rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(base_), 0, (int)span, kBufferWord3);
         const int tx = 2 * (threadIdx.x & 63);  // tx + 1 < TP always
         cv = tx < TW;
         c0 = (uint32_t)clampi(x_first + tx, 0, w - 1) * isw;
         c1 = (uint32_t)clampi(x_first + tx + 1, 0, w - 1) * isw;
-        pair = c1 == c0 + isw && isw <= 4;  // adjacent pixels, both bytes within 8 aligned bytes
     }
     __device__ __forceinline__ void issue(const uint8_t* plane_, int y0_, int rows_) {
         poff = (uint32_t)(plane_ - base);
         y0 = y0_; rows = rows_;
         if (!cv) return;  // one lane predicate for all rows (not one exec-mask region per row)
         const int wave = wave_id();
-        // wide loads: aligned start wvoff + soffset - pa, bytes o and o + isw of the 8
-        const uint32_t pa = poff & 3u, q = pa + c0, o = q & 3u;
-        wvoff = q & ~3u;
-        wsel = o | (0x0Cu << 8) | ((o + isw) << 16) | (0x0Cu << 24);  // 0x0C selects a zero byte
-        const uint32_t last = poff - pa + (uint32_t)clampi(y0 + rows - 1, 0, h - 1) * ish;
-        wide = __all((ish & 3u) == 0 && pair && last + wvoff + 8 <= span);
         if (y0 >= 0 && y0 + rows <= h) {
             // strip inside the frame: row offsets step by 4 rows, no clamping
             const uint32_t s0 = poff + (uint32_t)(y0 + wave) * ish, step = (uint32_t)(kThreads / 64) * ish;
-            if (wide) {
-#pragma unroll
-                for (int rb = 0; rb < kRowsPerWave; ++rb)
-                    if (rows == kStripMax || wave + rb * (kThreads / 64) < rows) {
-                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)wvoff, (int)(s0 - pa + rb * step), 0);
-                        b0[rb] = v[0];
-                        b1[rb] = v[1];
-                    }
-                return;
-            }
             if (rows == kStripMax) {  // full strip: every row of every wave
 #pragma unroll
                 for (int rb = 0; rb < kRowsPerWave; ++rb) {
@@ -253,19 +224,10 @@ struct Stager<uint8_t, _Float16> {
             const int ty = wave + rb * (kThreads / 64);
             if (ty < rows) {
                 const uint32_t soff = poff + (uint32_t)clampi(y0 + ty, 0, h - 1) * ish;
-                if (wide) {
-                    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)wvoff, (int)(soff - pa), 0);
-                    b0[rb] = v[0];
-                    b1[rb] = v[1];
-                } else {
-                    b0[rb] = load_byte(rsrc, c0, soff);
-                    b1[rb] = load_byte(rsrc, c1, soff);
-                }
+                b0[rb] = load_byte(rsrc, c0, soff);
+                b1[rb] = load_byte(rsrc, c1, soff);
             }
         }
-    }
-    __device__ __forceinline__ uint32_t packed(int rb) const {
-        return wide ? __builtin_amdgcn_perm(b1[rb], b0[rb], wsel) : (b1[rb] << 16) | b0[rb];
     }
     __device__ __forceinline__ void commit(_Float16* tile, int TP) {
         const int wave = wave_id(), lane = threadIdx.x & 63;
@@ -274,11 +236,11 @@ struct Stager<uint8_t, _Float16> {
             const int step = (kThreads / 64) * TP / 2;  // half2 elements per 4 rows (TP is even)
             if (rows == kStripMax) {
 #pragma unroll
-                for (int rb = 0; rb < kRowsPerWave; ++rb) dst[rb * step] = packed_bytes_to_half2(packed(rb));
+                for (int rb = 0; rb < kRowsPerWave; ++rb) dst[rb * step] = bytes_to_half2(b0[rb], b1[rb]);
             } else {
 #pragma unroll
                 for (int rb = 0; rb < kRowsPerWave; ++rb)
-                    if (wave + rb * (kThreads / 64) < rows) dst[rb * step] = packed_bytes_to_half2(packed(rb));
+                    if (wave + rb * (kThreads / 64) < rows) dst[rb * step] = bytes_to_half2(b0[rb], b1[rb]);
             }
         }
         for (int k0 = 128; k0 < TW; k0 += 128) {
@@ -294,76 +256,6 @@ struct Stager<uint8_t, _Float16> {
         }
     }
 };
-
-// ---- matrix-core passes (8-bit input) ------------------------------------------------------------
-// Each pass of a fragment is a banded product with the Toeplitz tap matrix T[c][x] = w_{c-x},
-// c - x in [0, 2r], run on v_mfma_f32_16x16x32_f16 (fp32 accumulation).  An fp32 tap w is split into
-// fp16 w_hi = fp16(w) and w_lo' = fp16((w - w_hi) 2^11); products with the two parts go to separate
-// accumulators, summed as C_hi + 2^-11 C_lo, so the taps keep about 22 significant bits while every
-// product is exact.
-typedef _Float16 h8v __attribute__((ext_vector_type(8)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-
-constexpr int kMfmaRmax = 48;    // radii taken by the matrix-core path (at most 4 chunks per tile)
-constexpr int kMfmaChunks = 4;   // 32-wide chunks per 16-wide output tile: (16 t + 15 + 2r) / 32 - t / 2 + 1
-constexpr int kMfmaCols = 32;    // output columns of a fragment (two 16-column tiles)
-constexpr int kTapTabLead = 32;  // table entry k + kTapTabLead packs taps (w_k, w_{k+1}), zero off [0, 2r]
-constexpr int kTapTabN = 2 * kMfmaRmax + 80;  // operand reads reach entry 2r + 78
-constexpr float kTapLoScale = 2048.0f;
-
-// Staged columns: whole chunks covering the right output tile's band.
-__host__ __device__ inline int mfma_tile_cols(int r) { return 32 * ((kMfmaCols - 1 + 2 * r) / 32 + 1); }
-// Staged (and horizontally filtered) rows for a fragment bh rows tall: whole chunks covering the
-// last 16-row output tile's band.
-__host__ __device__ inline int mfma_rows(int r, int bh) { return 32 * ((16 * ((bh + 15) / 16) - 1 + 2 * r) / 32 + 1); }
-// Pitches in halves, = 8 (mod 64): 16-byte operand reads of eight consecutive rows (tile) or
-// columns (intermediate) cover the 32 banks once.
-__host__ __device__ inline int mfma_pitch(int n) { return round_up(n - 8, 64) + 8; }
-
-struct MfmaLayout {
-    int TP, IP;  // tile row pitch, intermediate column pitch (halves)
-    size_t inter_off, tab_off, bytes;
-};
-
-// LDS of the matrix-core path: tile strip (SR rows), intermediate hi and lo (32 columns of TH rows),
-// tap tables.
-__host__ __device__ inline MfmaLayout mfma_layout(int r, int TH, int SR) {
-    MfmaLayout m;
-    m.TP = mfma_pitch(mfma_tile_cols(r));
-    m.IP = mfma_pitch(TH);
-    m.inter_off = kTileLead + align16((size_t)round_up(SR, 16) * m.TP * 2);
-    m.tab_off = m.inter_off + (size_t)2 * kMfmaCols * m.IP * 2;
-    m.bytes = m.tab_off + 2 * kTapTabN * 4;
-    return m;
-}
-
-__device__ __forceinline__ uint32_t pack_h2(_Float16 a, _Float16 b) {
-    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
-}
-
-// Tap tables: hi[k + lead] = (w_hi[k], w_hi[k+1]), lo likewise with the scaled low parts.
-__device__ __forceinline__ void build_tap_tables(uint32_t* hi, uint32_t* lo, const float* __restrict__ w, int r) {
-    for (int e = threadIdx.x; e < kTapTabN; e += kThreads) {
-        const int k = e - kTapTabLead;
-        const float w0 = (k >= 0 && k <= 2 * r) ? w[k] : 0.0f;
-        const float w1 = (k + 1 >= 0 && k + 1 <= 2 * r) ? w[k + 1] : 0.0f;
-        const _Float16 h0 = (_Float16)w0, h1 = (_Float16)w1;
-        hi[e] = pack_h2(h0, h1);
-        lo[e] = pack_h2((_Float16)((w0 - (float)h0) * kTapLoScale), (_Float16)((w1 - (float)h1) * kTapLoScale));
-    }
-}
-
-// Toeplitz operand of chunk kc (kc >= t / 2) for 16-wide output tile t: lane (m = lane % 16,
-// g = lane / 16) holds T[32 kc + 8 g + j][16 t + m] = w_{32 kc + 8 g + j - 16 t - m}, j = 0..7 — the B
-// operand of the horizontal pass (t a column tile) and the A operand of the vertical one (t a row
-// tile; A and B share this lane layout with the roles of rows and columns exchanged).
-__device__ __forceinline__ h8v tap_operand(const uint32_t* tab, int kc, int t, int lane) {
-    const int k0 = 32 * kc + 8 * (lane >> 4) - 16 * t - (lane & 15) + kTapTabLead;  // 1 .. 2r + 72
-    uint32_t u[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) u[i] = tab[k0 + 2 * i];
-    return __builtin_bit_cast(h8v, u);
-}
 
 // ---- fragments of a launch ---------------------------------------------------------------------
 // Narrow a fragment to output tile `sub` of its L-level split: tiles of
@@ -403,11 +295,14 @@ __device__ __forceinline__ void copy_fragment(const Frag& F, int c_lo, int c_hi)
 // One fragment: stage its padded tile strip by strip (the next strip's loads
 // in flight while the current one is computed), horizontal pass into the
 // column-major intermediate, vertical pass into the output.
-// Vector path: staged tile, horizontal pass into the fp32 column-major intermediate, vertical pass.
 template <typename TIn, typename TOut, typename TS, typename TC>
-__device__ __forceinline__ void fragment_passes(const FwdLaunch& a, int gid, int r, const Frag& F, int c_lo,
-                                                int c_hi, const TC* __restrict__ wts, unsigned char* smem) {
+__device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, int r, const Frag& F, int c_lo,
+                                                 int c_hi, const TC* __restrict__ wts, unsigned char* smem) {
     const FrameDesc& d = *F.fd;
+    if (r == 0) {
+        copy_fragment<TIn, TOut>(F, c_lo, c_hi);
+        return;
+    }
     const int tid = threadIdx.x;
     const TC* __restrict__ w = wts + (size_t)gid * a.wstride;
     const Geom g = geom(r, F.bw, F.bh);
@@ -475,160 +370,6 @@ __device__ __forceinline__ void fragment_passes(const FwdLaunch& a, int gid, int
             __syncthreads();  // next strip staged; every thread is past the previous vertical pass
         }
     }
-}
-
-// Matrix-core path (8-bit input, fragments up to 32 wide, r <= 48).  Both passes are banded products
-// on v_mfma_f32_16x16x32_f16.  Horizontal: staged rows (A) times the tap Toeplitz matrix (B) per
-// 16-column output tile; its fp32 result is written to LDS as an fp16 pair I = I_hi + I_lo (I_hi =
-// fp16(I), I_lo = fp16(I - I_hi)), column-major.  Vertical: the tap Toeplitz matrix (A, rows = output
-// rows) times the intermediate (B) per 16 x 16 output tile, as w_hi I_hi + w_hi I_lo + 2^-11 w_lo' I_hi
-// (the dropped w_lo I_lo term is below 2^-23 of the output).  Row and column chunks of 32 are anchored
-// at the fragment's nominal top-left corner (unclipped) minus r, so a split tile, a strip height, a
-// merged pair of 32-row fragments (other pairs are filtered one fragment at a time) or a translation
-// of frame and tiling together groups every sum the same way.
-template <typename TIn, typename TOut>
-__device__ __forceinline__ void fragment_mfma(const FwdLaunch& a, int gid, int r, const Frag& F, int c_lo, int c_hi,
-                                              const float* __restrict__ wts, unsigned char* smem) {
-    const FrameDesc& d = *F.fd;
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    const int m16 = lane & 15, g4 = lane >> 4;
-    const float* __restrict__ w = wts + (size_t)gid * a.wstride;
-    // chunk anchor: the fragment's nominal corner (before clipping to the frame; a split tile or a
-    // merged pair keeps its fragment's)
-    const int xa = d.p.origin_x + F.bx * d.p.block, ya = d.p.origin_y + F.by * d.p.block;
-    const int xoff = F.xa - xa, yoff = F.ya - ya;
-    const int TH = mfma_rows(r, yoff + F.bh);
-    int SR = min(min(a.strip_rows, kStripMax), TH);
-    if (SR < TH) SR = max(16, SR & ~15);  // whole 16-row tiles per strip
-    const MfmaLayout ml = mfma_layout(r, TH, SR);
-    const int TW = mfma_tile_cols(r), TP = ml.TP, IP = ml.IP;
-    _Float16* tile = reinterpret_cast<_Float16*>(smem + kTileLead);
-    _Float16* ihi = reinterpret_cast<_Float16*>(smem + ml.inter_off);  // [column][row]
-    _Float16* ilo = ihi + kMfmaCols * IP;
-    uint32_t* tab_hi = reinterpret_cast<uint32_t*>(smem + ml.tab_off);
-    uint32_t* tab_lo = tab_hi + kTapTabN;
-    const TIn* in = static_cast<const TIn*>(d.in);
-    TOut* out = static_cast<TOut*>(d.out);
-    const int nst = (TH + SR - 1) / SR;
-    const int nunits = (c_hi - c_lo) * nst;
-    Stager<TIn, _Float16> st;
-    const int64_t span = (int64_t)(d.c - 1) * d.isc + (int64_t)(d.h - 1) * d.ish + (int64_t)(d.w - 1) * d.isw + 1;
-    st.setup(xa - r, TW, d.w, d.isw, d.ish, d.h, in, (uint32_t)span);
-    st.issue(in + c_lo * d.isc, ya - r, SR);
-    build_tap_tables(tab_hi, tab_lo, w, r);
-    // output tiles: columns n_lo..n_hi, rows mt_lo..mt_hi (16 each, fragment coordinates)
-    const int n_lo = xoff >> 4, n_hi = (xoff + F.bw - 1) >> 4, nn = n_hi - n_lo + 1;
-    const int mt_lo = yoff >> 4, nmt = ((yoff + F.bh - 1) >> 4) - mt_lo + 1;
-    // horizontal pass: with two column tiles waves 0, 2 take the left one and 1, 3 the right
-    const int hn = nn == 2 ? n_lo + (wave & 1) : n_lo;
-    const int hrt0 = nn == 2 ? (wave >> 1) : wave, hrts = nn == 2 ? 2 : 4;
-    const int hnk = (16 * hn + 15 + 2 * r) / 32 + 1;
-    st.commit(tile, TP);
-    __syncthreads();
-    h8v bh[kMfmaChunks], bl[kMfmaChunks];
-#pragma unroll
-    for (int i = 0; i < kMfmaChunks; ++i)
-        if (i < hnk) {
-            bh[i] = tap_operand(tab_hi, i, hn, lane);
-            bl[i] = tap_operand(tab_lo, i, hn, lane);
-        }
-    const _Float16* arow = tile + m16 * TP + 8 * g4;
-    for (int u = 0; u < nunits; ++u) {
-        const int cu = u / nst, sidx = u - cu * nst, c = c_lo + cu;
-        const int s0 = sidx * SR, rows = min(SR, TH - s0);  // a multiple of 16
-        if (u + 1 < nunits) {
-            const int cn = (u + 1) / nst, sn = (u + 1) - cn * nst;
-            st.issue(in + (c_lo + cn) * d.isc, ya - r + sn * SR, min(SR, TH - sn * SR));
-        }
-        for (int rt = hrt0; rt < (rows >> 4); rt += hrts) {
-            f4v ch = {0.0f, 0.0f, 0.0f, 0.0f}, cl = {0.0f, 0.0f, 0.0f, 0.0f};
-            const _Float16* ar = arow + 16 * rt * TP;
-#pragma unroll
-            for (int i = 0; i < kMfmaChunks; ++i)
-                if (i < hnk) {
-                    const h8v av = *reinterpret_cast<const h8v*>(ar + 32 * i);
-                    ch = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bh[i], ch, 0, 0, 0);
-                    cl = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bl[i], cl, 0, 0, 0);
-                }
-            // lane holds rows 16 rt + 4 g4 + 0..3 of column 16 hn + m16
-            _Float16 hv[4], lv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float v = fmaf(cl[i], 1.0f / kTapLoScale, ch[i]);
-                hv[i] = (_Float16)v;
-                lv[i] = (_Float16)(v - (float)hv[i]);
-            }
-            const int at = (16 * hn + m16) * IP + s0 + 16 * rt + 4 * g4;
-            *reinterpret_cast<uint2*>(ihi + at) = make_uint2(pack_h2(hv[0], hv[1]), pack_h2(hv[2], hv[3]));
-            *reinterpret_cast<uint2*>(ilo + at) = make_uint2(pack_h2(lv[0], lv[1]), pack_h2(lv[2], lv[3]));
-        }
-        __syncthreads();  // the tile is free; the channel's intermediate may be complete
-        if (sidx == nst - 1) {
-            // vertical pass: output tile (mt, nt) per wave
-            TOut* oc = out + c * d.osc;
-            for (int t = wave; t < nmt * nn; t += kThreads / 64) {
-                const int mt = mt_lo + t / nn, nt = n_lo + t % nn;
-                const int kc0 = mt >> 1, kc1 = (16 * mt + 15 + 2 * r) >> 5;
-                f4v c1 = {0.0f, 0.0f, 0.0f, 0.0f}, c2 = {0.0f, 0.0f, 0.0f, 0.0f};
-                const _Float16* bcol = ihi + (16 * nt + m16) * IP + 8 * g4;
-                for (int kc = kc0; kc <= kc1; ++kc) {
-                    const h8v ah = tap_operand(tab_hi, kc, mt, lane);
-                    const h8v al = tap_operand(tab_lo, kc, mt, lane);
-                    const h8v xh = *reinterpret_cast<const h8v*>(bcol + 32 * kc);
-                    const h8v xl = *reinterpret_cast<const h8v*>(bcol + kMfmaCols * IP + 32 * kc);
-                    c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, xh, c1, 0, 0, 0);
-                    c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, xl, c1, 0, 0, 0);
-                    c2 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, xh, c2, 0, 0, 0);
-                }
-                // lane holds output rows 16 mt + 4 g4 + 0..3 of column 16 nt + m16 (fragment coordinates)
-                const int x = 16 * nt + m16 - xoff;
-                if (x >= 0 && x < F.bw) {
-                    TOut* o = oc + (int64_t)(F.xa + x) * d.osw;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int y = 16 * mt + 4 * g4 + i - yoff;
-                        if (y >= 0 && y < F.bh)
-                            o[(int64_t)(F.ya + y) * d.osh] = to_out<TOut, float>(fmaf(c2[i], 1.0f / kTapLoScale, c1[i]));
-                    }
-                }
-            }
-        }
-        if (u + 1 < nunits) {
-            st.commit(tile, TP);
-            __syncthreads();  // next strip staged; every wave is past the previous vertical pass
-        }
-    }
-}
-
-template <typename TIn, typename TOut, typename TS, typename TC>
-__device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, int r, const Frag& F, int c_lo,
-                                                 int c_hi, const TC* __restrict__ wts, unsigned char* smem) {
-    if (r == 0) {
-        copy_fragment<TIn, TOut>(F, c_lo, c_hi);
-        return;
-    }
-    if constexpr (std::is_same<TS, _Float16>::value) {
-        const int B = F.fd->p.block;
-        if (B <= kMfmaCols && r <= kMfmaRmax) {
-            const int yb = F.fd->p.origin_y + F.by * B + B;  // (upper) fragment's bottom edge
-            if (F.ya + F.bh > yb && (B & 31)) {
-                // A merged pair of fragments less than a row chunk tall: the lower one's chunks are
-                // anchored at its own corner, so the two are filtered one after the other.
-                Frag U = F, D = F;
-                U.bh = yb - F.ya;
-                D.by = F.by + 1;
-                D.ya = yb;
-                D.bh = F.ya + F.bh - yb;
-                fragment_mfma<TIn, TOut>(a, gid, r, U, c_lo, c_hi, wts, smem);
-                __syncthreads();  // the upper fragment's LDS reads are done
-                fragment_mfma<TIn, TOut>(a, gid, r, D, c_lo, c_hi, wts, smem);
-            } else {
-                fragment_mfma<TIn, TOut>(a, gid, r, F, c_lo, c_hi, wts, smem);
-            }
-            return;
-        }
-    }
-    fragment_passes<TIn, TOut, TS, TC>(a, gid, r, F, c_lo, c_hi, wts, smem);
 }
 
 // Work items are taken from the queue (by decreasing radius, so the costliest
@@ -1018,17 +759,7 @@ size_t forward_lds_bytes(int in_dtype, int r_cap, int tile_w, int tile_h, int st
     const int es = stage_size(in_dtype), ec = compute_size(in_dtype);
     // 8-bit input: (-r) mod 4 leading columns; 2r + ((-r) mod 4) never decreases with r, so r_cap sizes them
     const int TW = g.TW + (in_dtype == FOV_U8 ? ((-r_cap) & 3) : 0);
-    size_t bytes = kTileLead + align16((size_t)rows * tile_pitch(TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec;
-    if (in_dtype == FOV_U8 && r_cap > 0) {
-        // fragments with r <= 48 (at most 32 wide and tall) take the matrix-core path, which
-        // stages whole fragments, a split tile's included; tile_h above 32 is a merged pair
-        const int rm = std::min(r_cap, kMfmaRmax);
-        const int TH = mfma_rows(rm, std::max(tile_h, kMfmaCols));
-        int sr = std::min(std::min(strip_rows, kStripMax), TH);
-        if (sr < TH) sr = std::max(16, sr & ~15);
-        bytes = std::max(bytes, mfma_layout(rm, TH, sr).bytes);
-    }
-    return bytes + 64;
+    return kTileLead + align16((size_t)rows * tile_pitch(TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec + 64;
 }
 
 fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,
