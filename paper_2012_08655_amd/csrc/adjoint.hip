@@ -155,6 +155,10 @@ __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, 
     const int by_lo = max(Q.by - K, 0), by_hi = min(Q.by + K, nby - 1);
     const int bx_lo = max(Q.bx - K, 0), bx_hi = min(Q.bx + K, nbx - 1);
     T* out = static_cast<T*>(d.out);
+    // The PAD rows above and the rows below bmax stay zero: staged once here, never written again
+    // (each round writes rows PAD .. PAD + bmax - 1 only; the first round's barrier orders this).
+    for (int i = tid; i < s.chunk_v * CS; i += kThreads) cols[i] = (T)0;  // the slots allocated (<= CB)
+    const int rg_lo = PAD / V, rg_hi = (PAD + s.bmax + V - 1) / V;  // row groups that can hold b's rows
     for (int c0 = 0; c0 < d.c; c0 += CB) {
         const int cc = min(CB, d.c - c0);
         T acc[CB][TASKS][kPV];
@@ -175,12 +179,13 @@ __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, 
                 const T* __restrict__ w = wts + (size_t)b * a.wstride;
                 const int xoff = a.r_cap - Fb.xa;
                 __syncthreads();  // the previous fragment's columns are no longer read
-                // per channel, column x of the tile: PAD zero rows, b's rows, zeros to the pitch
-                const int nrg = PB / V;
+                // per channel, column x of the tile: b's rows from row PAD on (zeros past its height
+                // and outside its reach)
+                const int nrg = rg_hi - rg_lo;
                 const int items = Q.bw * nrg;
                 for (int i = tid; i < cc * items; i += kThreads) {
                     const int ch = i / items, j = i - ch * items;
-                    const int rg = j / Q.bw, x = j - rg * Q.bw;
+                    const int rg = rg_lo + j / Q.bw, x = j - (j / Q.bw) * Q.bw;
                     const int gx = Q.xa + x;
                     const bool inx = gx >= rx0 && gx <= rx1;
                     const T* src = scratch + ((size_t)b * s.cmax + c0 + ch) * s.bmax * s.sw;
