@@ -387,7 +387,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rates", default="120,480,1920", help="offered frames/s of the serving traces")
-    ap.add_argument("--serve-seconds", type=float, default=5.0, help="measured seconds per serving trace")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="measured seconds per serving trace")
     ap.add_argument("--serve-budget-mib", type=int, default=256)
     ap.add_argument("--serve-max-batch", type=int, default=16)
     ap.add_argument("--serve-graph", type=int, default=1, help="1: the server replays captured hipGraphs")
