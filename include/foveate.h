@@ -98,7 +98,7 @@ fov_status foveate_grid(int32_t h, int32_t w, const fov_params* p, int32_t* nbx,
 
 /*
  * Geisler-Perry blur model (Appendix "Choosing the Standard Deviation", Eqs.
- * 3-6) as ramp parameters.  With CT0 = 1/64, alpha = 0.106 and e2 = 2.3 (the
+ * 2-6) as ramp parameters.  With CT0 = 1/64, alpha = 0.106 and e2 = 2.3 (the
  * constants the paper adopts), the cutoff f_c_deg(e) = e2 ln(1/CT0) /
  * (alpha (e + e2)) cycles/degree, f_c_pix = 0.5 f_c_deg / f_max cycles/pixel,
  * the eccentricity e = d / d_corner * e_corner degrees for a pixel distance d
@@ -130,7 +130,8 @@ fov_status foveate_fragment_shift(double fix_x, double fix_y, int32_t block, int
                                   int32_t* origin_y);
 
 /*
- * Per-fragment plan (Alg. 1 "grid of blurring strengths"), computed ON THE
+ * Per-fragment plan (the per-fragment blur strengths Alg. 1 sets up on the
+ * host), computed ON THE
  * DEVICE by the same code the kernels run: sigma_out[by*nbx+bx] (double) and
  * r_out[...] (int32), both device arrays of nby*nbx entries owned by the
  * caller.  sigma_out may be NULL.  Asynchronous on `stream`.
@@ -146,8 +147,9 @@ fov_status foveate_plan_host(int32_t h, int32_t w, const fov_params* p, double* 
                              int32_t* r_out);
 
 /*
- * Foveate n frames: out = A_p(in) (Sec. 2, Alg. 1 steps "place padded
- * fragment into shared memory" .. "write result to output array").
+ * Foveate n frames: out = A_p(in) (Sec. 2; the device part of Alg. 1: the
+ * padded fragment staged on chip, a horizontal pass, a vertical pass, the
+ * store).
  *   in, out : same (n, c, h, w); dtype pairs u8->u8, u8->f32 (raw 0..255),
  *             f32->f32, f64->f64.  out must not overlap in (FOV_EALIAS).
  *   p       : np parameter sets, np == n (one per frame) or np == 1 (shared).
@@ -264,7 +266,7 @@ fov_status foveate_tuning_load(const char* path);
  *
  * A request loop for frames that arrive one at a time (each with its own
  * size and gaze), in the spirit of the paper's per-frame asynchronous loop
- * (Alg. 1, "with every frame"), with continuous batching: a scheduler thread
+ * (the per-frame loop of Alg. 1), with continuous batching: a scheduler thread
  * admits queued frames while the bytes of admitted, unfinished frames stay
  * within an HBM budget, launches everything admitted as one batched forward
  * (the queue of foveate_forward_batch) on one of several streams, and admits

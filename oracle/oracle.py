@@ -16,7 +16,7 @@ adds two NumPy helpers that are themselves definitions:
 * :func:`fragment_shift` -- the tiling origin that centres one fragment on
   the fixation (Alg. 1, Sec. 3 "SSIM"), in plain Python.
 * :func:`csf_sigma` / :func:`csf_sigma_map` -- the Geisler-Perry blur model
-  (Appendix "Choosing the Standard Deviation", Eqs. 3-6) evaluated step by
+  (Appendix "Choosing the Standard Deviation", Eqs. 2-6) evaluated step by
   step in NumPy, per distance or per fragment midpoint.
 
 Arrays are [c, h, w] (or [n, c, h, w]) float64; frame parameters are plain
@@ -139,33 +139,33 @@ def fragment_shift(p: Mapping) -> dict:
     return out
 
 
-# Contrast-threshold model constants the paper adopts (Eq. 3 and the text after it).
+# Contrast-threshold model constants the paper adopts (Eq. 2 and the text after it).
 CSF_CT0 = 1.0 / 64.0
 CSF_ALPHA = 0.106
 CSF_E2 = 2.3
 
 
 def csf_contrast_threshold(f_cpd, e_deg):
-    """Eq. 3: contrast needed to detect a grating of f cycles/degree at
+    """Eq. 2: contrast needed to detect a grating of f cycles/degree at
     eccentricity e degrees."""
     return CSF_CT0 * np.exp(CSF_ALPHA * f_cpd * (e_deg + CSF_E2) / CSF_E2)
 
 
 def csf_cutoff_cpd(e_deg):
-    """Eq. 4: the frequency whose threshold is full contrast (CT = 1)."""
+    """Eq. 3: the frequency whose threshold is full contrast (CT = 1)."""
     return CSF_E2 / (CSF_ALPHA * (e_deg + CSF_E2)) * np.log(1.0 / CSF_CT0)
 
 
 def csf_sigma(d_px, h: int, w: int, e_corner: float, f_max: float = 0.0):
     """sigma (pixels) at pixel distance d from the fixation, for an h x w frame
-    whose corner is e_corner degrees away (Eqs. 4-6).  f_max <= 0 takes the
+    whose corner is e_corner degrees away (Eqs. 3-6).  f_max <= 0 takes the
     foveal cutoff f_c_deg(0) as the highest resolvable frequency."""
     if f_max <= 0:
         f_max = csf_cutoff_cpd(0.0)
     d_corner = np.hypot((w - 1) / 2.0, (h - 1) / 2.0)  # half-diagonal, pixel-centre coordinates
     e = np.asarray(d_px, dtype=np.float64) / d_corner * e_corner  # Eq. 5
-    f_c_deg = csf_cutoff_cpd(e)  # Eq. 4
-    f_c_pix = 0.5 * f_c_deg / f_max  # cycles per pixel
+    f_c_deg = csf_cutoff_cpd(e)  # Eq. 3
+    f_c_pix = 0.5 * f_c_deg / f_max  # Eq. 4, cycles per pixel
     return 1.0 / (2.0 * np.pi * f_c_pix)  # Eq. 6
 
 

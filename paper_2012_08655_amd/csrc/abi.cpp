@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -140,6 +141,50 @@ fov_status workspace(hipStream_t stream, size_t dev_bytes, size_t host_bytes, Wo
     }
     *out = &w;
     return FOV_OK;
+}
+
+// Launch attributes of the kernels, per device: dynamic-LDS permission and
+// occupancy queries, behind one lock so that concurrent first launches from
+// several threads neither race nor pair one size with another's answer.
+namespace {
+std::mutex g_attr_mu;
+std::map<std::pair<int, const void*>, bool> g_lds_set;
+std::map<std::tuple<int, const void*, size_t>, int> g_occ;
+}  // namespace
+
+fov_status allow_dyn_lds(const void* kern, size_t lds_limit) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    if (g_lds_set.count({dev, kern})) return FOV_OK;
+    hipFuncAttributes fa;
+    e = hipFuncGetAttributes(&fa, kern);
+    if (e != hipSuccess) return hip_error(e, "hipFuncGetAttributes");
+    const size_t dyn_max = lds_limit > fa.sharedSizeBytes ? lds_limit - fa.sharedSizeBytes : 0;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max);
+    if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(dynamic LDS)");
+    g_lds_set[{dev, kern}] = true;
+    return FOV_OK;
+}
+
+int occupancy_of(const void* kern, size_t lds) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    const auto key = std::make_tuple(dev, kern, lds);
+    auto it = g_occ.find(key);
+    if (it != g_occ.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kThreads, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        nb = 0;
+    }
+    g_occ[key] = nb;
+    return nb;
 }
 
 size_t dtype_size(int dt) {
@@ -356,11 +401,14 @@ CallShape call_shape(const std::vector<FrameDesc>& frames) {
 fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream,
                        const LaunchCfg* cfg_in, bool profile) {
     fov_status s;
-    const DeviceInfo* dev = nullptr;
-    if ((s = device_info(&dev)) != FOV_OK) return s;
     const int nf = (int)frames.size();
     if (nf == 0) return FOV_OK;
     const CallShape cs = call_shape(frames);
+    if (cs.r_cap >= kRadiusLimit)
+        return set_error(FOV_ERANGE, "a fragment radius exceeds " + std::to_string(kRadiusLimit - 1) +
+                                         " pixels; no workgroup can stage its window");
+    const DeviceInfo* dev = nullptr;
+    if ((s = device_info(&dev)) != FOV_OK) return s;
     const LaunchCfg cfg = cfg_in ? *cfg_in : select_cfg(frames, in_dtype, out_dtype, cs);
     const int L = cfg.split_log2;
     if ((cs.nfrag << (2 * L)) > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
@@ -480,6 +528,9 @@ fov_status run_backward(const fov_tensor* go, const fov_tensor* gi, const fov_pa
     std::vector<FrameDesc> frames;
     frames.reserve(go->n);
     for (int i = 0; i < go->n; ++i) frames.push_back(make_frame_desc(*go, *gi, i, p[np == 1 ? 0 : i]));
+    if (call_shape(frames).r_cap >= kRadiusLimit)
+        return set_error(FOV_ERANGE, "a fragment radius exceeds " + std::to_string(kRadiusLimit - 1) +
+                                         " pixels; no workgroup can stage its window");
     const int es = go->dtype == FOV_F64 ? 8 : 4;
     size_t f0 = 0;
     while (f0 < frames.size()) {
@@ -636,7 +687,7 @@ fov_status foveate_csf_params(int32_t h, int32_t w, double e_corner_deg, double 
     if (!std::isfinite(e_corner_deg) || e_corner_deg <= 0) return set_error(FOV_EINVAL, "e_corner must be > 0");
     if (!std::isfinite(f_max_cpd) || !std::isfinite(cap) || cap <= 0)
         return set_error(FOV_EINVAL, "f_max must be finite and cap > 0");
-    // constants of the contrast-threshold model the paper adopts (Eq. 3)
+    // constants of the contrast-threshold model the paper adopts (Eq. 2)
     const double ct0 = 1.0 / 64.0, alpha = 0.106, e2 = 2.3;
     const double ln_inv_ct0 = std::log(1.0 / ct0);
     const double f_max = f_max_cpd > 0 ? f_max_cpd : ln_inv_ct0 / alpha;  // f_c_deg at e = 0

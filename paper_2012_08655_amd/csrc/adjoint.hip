@@ -269,33 +269,13 @@ __global__ __launch_bounds__(kThreads) void fov_adj_v_kernel(const FwdLaunch a, 
 }
 
 template <typename T, int TASKS, int CB>
-struct AdjSlot {
-    static bool configured;
-};
-template <typename T, int TASKS, int CB>
-bool AdjSlot<T, TASKS, CB>::configured = false;
-
-fov_status set_dyn_lds(const void* k, size_t lds_limit) {
-    hipFuncAttributes fa;
-    hipError_t e = hipFuncGetAttributes(&fa, k);
-    if (e != hipSuccess) return hip_error(e, "hipFuncGetAttributes(adjoint)");
-    const size_t dyn_max = lds_limit > fa.sharedSizeBytes ? lds_limit - fa.sharedSizeBytes : 0;
-    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max);
-    if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(adjoint)");
-    return FOV_OK;
-}
-
-template <typename T, int TASKS, int CB>
 fov_status launch_typed(const FwdLaunch& a, const AdjShape& s, const PlanBuffers& plan, void* scratch,
                         hipStream_t stream, size_t lds_limit) {
     auto kh = fov_adj_h_kernel<T>;
     auto kv = fov_adj_v_kernel<T, TASKS, CB>;
     fov_status st;
-    if (!AdjSlot<T, TASKS, CB>::configured) {
-        if ((st = set_dyn_lds((const void*)kh, lds_limit)) != FOV_OK) return st;
-        if ((st = set_dyn_lds((const void*)kv, lds_limit)) != FOV_OK) return st;
-        AdjSlot<T, TASKS, CB>::configured = true;
-    }
+    if ((st = allow_dyn_lds((const void*)kh, lds_limit)) != FOV_OK) return st;
+    if ((st = allow_dyn_lds((const void*)kv, lds_limit)) != FOV_OK) return st;
     const T* wts = static_cast<const T*>(plan.weights);
     T* sc = static_cast<T*>(scratch);
     hipLaunchKernelGGL(kh, dim3(a.nfrag), dim3(kThreads), adjoint_lds_h(s, sizeof(T)), stream, a, s,

@@ -31,8 +31,8 @@ __host__ __device__ inline int grid_extent(int len, int origin, int B) {
     return (len - origin + B - 1) / B;
 }
 
-// Blur strength of fragment (bx, by) (Sec. 2: each fragment is blurred
-// according to the distance from its midpoint to the fixation point).
+// Blur strength of fragment (bx, by) (Sec. 2: a fragment's blur strength
+// follows how far its midpoint lies from the fixation point).
 // Midpoint in pixel-centre coordinates; sigma(e) = 0 below e0, else
 // min(slope*(e - e0), cap).  IEEE double with no contraction so the host and
 // the device produce the same bits; sqrt is correctly rounded on both.
@@ -57,10 +57,17 @@ __host__ __device__ inline double clip_map_sigma(double m, double cap) {
     return s > 0.0 ? s : 0.0;
 }
 
-// Window radius: taps beyond 3 sigma are dropped (Appendix "Methods").
+// Largest radius radius_of reports.  Far beyond what a workgroup's on-chip
+// memory can stage, so a call that reaches it is refused (FOV_ERANGE) rather
+// than sized with an overflowed int.
+constexpr int kRadiusLimit = 1 << 20;
+
+// Window radius: taps beyond 3 sigma are dropped (Appendix "Methods").  The
+// bound is applied in double, before the conversion to int.
 __host__ __device__ inline int radius_of(double sigma) {
     if (!(sigma > 0.0)) return 0;
-    return (int)ceil(3.0 * sigma);
+    const double t = ceil(3.0 * sigma);
+    return t < (double)kRadiusLimit ? (int)t : kRadiusLimit;
 }
 
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }

@@ -114,4 +114,13 @@ int forward_occupancy(int in_dtype, int out_dtype, size_t lds);
 // Largest strip height the kernel stages at once.
 int forward_strip_max();
 
+// Let `kern` use all the dynamic LDS a workgroup may have on the current
+// device (done once per device and kernel; safe to call from any thread).
+fov_status allow_dyn_lds(const void* kern, size_t lds_limit);
+
+// Workgroups of kThreads threads with `lds` bytes of dynamic LDS each that
+// one CU of the current device holds at once; cached per device, kernel and
+// size (safe from any thread); 0 if the query fails.
+int occupancy_of(const void* kern, size_t lds);
+
 }  // namespace fov

@@ -38,8 +38,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <map>
-#include <mutex>
 #include <type_traits>
 
 namespace fov {
@@ -652,44 +650,13 @@ __global__ void fov_plan_kernel(FrameParams fp, int n, double* sigma_out, int32_
 }
 
 template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
-struct FwdSlot {
-    static bool configured;
-    static size_t occ_lds;
-    static int occ_blocks;
-};
-template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
-bool FwdSlot<TIn, TOut, TS, TC, PERSIST>::configured = false;
-template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
-size_t FwdSlot<TIn, TOut, TS, TC, PERSIST>::occ_lds = 0;
-template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
-int FwdSlot<TIn, TOut, TS, TC, PERSIST>::occ_blocks = 0;
-
-template <typename TIn, typename TOut, typename TS, typename TC, bool PERSIST>
 fov_status launch_main(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, hipStream_t stream,
                        size_t lds_limit, int cus, hipEvent_t ev_start, hipEvent_t ev_stop) {
-    using Slot = FwdSlot<TIn, TOut, TS, TC, PERSIST>;
     auto kern = fov_fwd_kernel<TIn, TOut, TS, TC, PERSIST>;
-    hipError_t e;
-    if (!Slot::configured) {
-        hipFuncAttributes fa;
-        e = hipFuncGetAttributes(&fa, (const void*)kern);
-        if (e != hipSuccess) return hip_error(e, "hipFuncGetAttributes(forward)");
-        const size_t dyn_max = lds_limit > fa.sharedSizeBytes ? lds_limit - fa.sharedSizeBytes : 0;
-        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max);
-        if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(forward)");
-        Slot::configured = true;
-    }
+    fov_status st = allow_dyn_lds((const void*)kern, lds_limit);
+    if (st != FOV_OK) return st;
     int grid = a.nslots;
-    if (PERSIST) {
-        if (Slot::occ_lds != lds) {
-            int nb = 0;
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)kern, kThreads, lds);
-            if (e != hipSuccess) return hip_error(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-            Slot::occ_blocks = std::max(nb, 1);
-            Slot::occ_lds = lds;
-        }
-        grid = std::max(1, std::min(a.nslots, Slot::occ_blocks * cus));
-    }
+    if (PERSIST) grid = std::max(1, std::min(a.nslots, std::max(occupancy_of((const void*)kern, lds), 1) * cus));
     if (ev_start || ev_stop) {
         // The dispatch itself stamps the events: no separate event packets (each would leave a
         // gap of several microseconds between the kernels of the stream).
@@ -701,7 +668,7 @@ fov_status launch_main(const FwdLaunch& a, size_t lds, const PlanBuffers& plan, 
                            (const TC*)plan.weights, (const int32_t*)plan.order, (const FrameDesc*)a.table,
                            (const int32_t*)a.prefix);
     }
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "forward kernel launch");
     return FOV_OK;
 }
@@ -778,20 +745,8 @@ fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_
 }
 
 int forward_occupancy(int in_dtype, int out_dtype, size_t lds) {
-    static std::mutex mu;
-    static std::map<std::pair<const void*, size_t>, int> cache;
     const void* k = forward_main_kernel(in_dtype, out_dtype, false);
-    if (!k) return 0;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find({k, lds});
-    if (it != cache.end()) return it->second;
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kThreads, lds) != hipSuccess) {
-        (void)hipGetLastError();
-        nb = 0;
-    }
-    cache[{k, lds}] = nb;
-    return nb;
+    return k ? occupancy_of(k, lds) : 0;
 }
 
 const void* forward_main_kernel(int in_dtype, int out_dtype, bool persist) {

@@ -196,6 +196,26 @@ def test_u8_frame_span_limit():
     assert "2^31" in N.lib().foveate_last_error().decode()
 
 
+def test_huge_sigma_is_refused_not_overflowed():
+    # 3 sigma beyond the int range must not wrap to a small radius (a frame silently copied):
+    # the host plan reports the radius bound, and forward/backward refuse the call with
+    # FOV_ERANGE before any device work, for the ramp and for a sigma map (bounded by its cap)
+    L = N.lib()
+    h, w = 64, 64
+    p = synth.params_dict(0, 0, 0, 1e9, 1e12, 32)
+    _, r = host_plan(h, w, p)
+    assert r.max() == 1 << 20 and r.min() > 0
+    a = fake_desc(N.FOV_F32, 1, 1, h, w, 0x10000000)
+    b = fake_desc(N.FOV_F32, 1, 1, h, w, 0x20000000)
+    for cap in (7.3e8, 1e12, 1e300):
+        pr = synth.params_dict(0, 0, 0, 1e9, cap, 32)
+        assert call_fwd(a, b, pr) == N.FOV_ERANGE, cap
+        arr = (N.FovParams * 1)(N.make_params(pr, sigma_map_ptr=0x30000000))
+        assert L.foveate_forward(ctypes.byref(a), ctypes.byref(b), arr, 1, None) == N.FOV_ERANGE, cap
+        assert L.foveate_backward(ctypes.byref(a), ctypes.byref(b), arr, 1, None) == N.FOV_ERANGE, cap
+        assert b"radius" in L.foveate_last_error()
+
+
 def test_fragment_shift_matches_oracle(orc):
     L = N.lib()
     rng = np.random.default_rng(21)

@@ -1,6 +1,6 @@
 """Geisler-Perry blur model on the GPU: frames foveated with the ramp that
 foveate_csf_params derives match the oracle, which evaluates the paper's
-Eqs. 3-6 per fragment and blurs with that sigma map."""
+Eqs. 2-6 per fragment and blurs with that sigma map."""
 import numpy as np
 import pytest
 import torch

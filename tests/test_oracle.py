@@ -294,10 +294,10 @@ def test_fragment_shift_makes_blur_follow_the_gaze(orc):
     assert np.max(np.abs(z1[..., r + k:120 - r] - z0[..., r:120 - k - r])) > 1e-3
 
 
-# ---- Geisler-Perry blur model (Appendix "Choosing the Standard Deviation", Eqs. 3-6) ------------
+# ---- Geisler-Perry blur model (Appendix "Choosing the Standard Deviation", Eqs. 2-6) ------------
 
 def test_csf_cutoff_inverts_the_contrast_threshold(orc):
-    # Eq. 4 is Eq. 3 solved for CT = 1 (full contrast)
+    # Eq. 3 is Eq. 2 solved for CT = 1 (full contrast)
     for e in (0.0, 0.5, 2.3, 10.0, 45.0):
         assert abs(orc.csf_contrast_threshold(orc.csf_cutoff_cpd(e), e) - 1.0) <= 1e-12
     # and a slightly higher frequency needs more than full contrast
@@ -314,7 +314,7 @@ def test_csf_sigma_closed_forms(orc):
     f0 = math.log(64.0) / 0.106
     assert abs(orc.csf_cutoff_cpd(0.0) - f0) <= 1e-12
     assert abs(orc.csf_sigma(dc / 2, h, w, ec, f_max=20.0) / orc.csf_sigma(dc / 2, h, w, ec) - 20.0 / f0) <= 1e-12
-    # sigma is affine in the pixel distance (Eq. 5 is linear, Eq. 4 is 1/(e + e2))
+    # sigma is affine in the pixel distance (Eq. 5 is linear, Eq. 3 is 1/(e + e2))
     d = np.linspace(0, 1500, 7)
     s = orc.csf_sigma(d, h, w, ec)
     assert np.max(np.abs(np.diff(s, 2))) <= 1e-12
