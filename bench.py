@@ -3,9 +3,11 @@
 
 One step = one 1080p RGB frame foveated by foveate_forward (plan, weights,
 tile staging, horizontal pass, vertical pass, u8 epilogue and foveal copies
-all run inside the one kernel launch).  Frames rotate over a pool resident in
-HBM (about 1.2 GB of inputs and outputs, larger than the 256 MB last-level
-cache) and every step draws a fresh fixation uniformly from the central half.
+all run inside the one kernel launch).  Step k reads and writes frame k mod
+pool of a pool resident in HBM (96 frames, about 1.2 GB of inputs and
+outputs by default) and draws a fresh fixation uniformly from the central
+half; the JSON line states how many pool frames and bytes the timed steps
+touched (fewer than the pool when there are fewer steps than frames).
 
 Prints one JSON line.  `roofline` prices the forward kernel's algorithmic
 FP32 FMA work (halo-inclusive separable count, foveal fragments zero) against
@@ -222,7 +224,7 @@ def serving_leg(rates, seconds, warm_s, budget_mib, max_batch, use_graph=True, s
                 for i in range(n):
                     _spin_until(lib, t0 + tr["t"][i])
                     N.check(lib.foveate_submit(srv._h, ctypes.byref(din[i]), ctypes.byref(dout[i]),
-                                               ctypes.byref(prm[i]), ctypes.byref(tk)))
+                                               ctypes.byref(prm[i]), None, ctypes.byref(tk)))
                     tickets[i] = tk.value
                     while oldest < i and retire(oldest):
                         oldest += 1
@@ -300,54 +302,39 @@ def batch_leg(reps=10, seed=11):
                                 "mpix_s": round(mpix / med_p * 1e3, 1)}}
 
 
-def host_pipeline_leg(frames=300, slots=3, seed=13):
+def host_pipeline_leg(frames=300, depth=4, distinct=8, seed=13):
     """End-to-end rate with the frames in pinned host memory (the paper's
-    165 Hz includes its transfers): per frame an H2D copy on one stream, the
-    foveation on the compute stream, a D2H copy on a third stream, ordered by
-    events and overlapped across frames through `slots` device buffers."""
+    165 Hz includes its transfers), through the library's host pipeline
+    (foveate_pipeline_*): per frame an upload, the foveation and a download,
+    overlapped across `depth` device slots.  `distinct` different pinned
+    frames are cycled, each step with its own central-half fixation."""
     import torch
     import synth
-    import paper_2012_08655_amd as fov
-    dev = torch.device("cuda:0")
+    from paper_2012_08655_amd.pipeline import HostPipeline
     rng = np.random.default_rng(seed)
-    src = torch.from_numpy(synth.grating_frame(H, W, C, seed=seed)).pin_memory()
-    host_in = [src.clone().pin_memory() for _ in range(slots)]
-    host_out = [torch.empty_like(src).pin_memory() for _ in range(slots)]
-    d_in = [torch.empty(src.shape, dtype=torch.uint8, device=dev) for _ in range(slots)]
-    d_out = [torch.empty_like(t) for t in d_in]
-    params = [synth.params_cfg2(rng) for _ in range(frames)]
-    s_h2d, s_d2h = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
-    comp = torch.cuda.current_stream()
-    h2d_done = [torch.cuda.Event() for _ in range(slots)]
-    fwd_done = [torch.cuda.Event() for _ in range(slots)]
-    d2h_done = [torch.cuda.Event() for _ in range(slots)]
+    host_in = [torch.from_numpy(synth.grating_frame(H, W, C, seed=seed + k)).pin_memory() for k in range(distinct)]
+    nbuf = depth + 1
+    host_out = [torch.empty_like(host_in[0]).pin_memory() for _ in range(nbuf)]
+    params = [synth.params_cfg2(rng) for _ in range(frames + 2 * depth)]
+    with HostPipeline(H * W * C, depth=depth) as pl:
 
-    def run(n):
-        for i in range(n):
-            k = i % slots
-            if i >= slots:
-                s_h2d.wait_event(fwd_done[k])  # the forward of frame i - slots has read d_in[k]
-            with torch.cuda.stream(s_h2d):
-                d_in[k].copy_(host_in[k], non_blocking=True)
-                h2d_done[k].record(s_h2d)
-            comp.wait_event(h2d_done[k])
-            if i >= slots:
-                comp.wait_event(d2h_done[k])  # the D2H of frame i - slots has read d_out[k]
-            fov.forward(d_in[k], params[i], out=d_out[k], layout="HWC", stream=comp)
-            fwd_done[k].record(comp)
-            s_d2h.wait_event(fwd_done[k])
-            with torch.cuda.stream(s_d2h):
-                host_out[k].copy_(d_out[k], non_blocking=True)
-                d2h_done[k].record(s_d2h)
-        torch.cuda.synchronize()
+        def run(n, first):
+            tickets = []
+            for i in range(n):
+                if i >= depth:
+                    pl.wait(tickets[i - depth])  # at most `depth` frames in flight
+                tickets.append(pl.submit(host_in[i % distinct], params[first + i], out=host_out[i % nbuf]))
+            for t in tickets[max(0, n - depth):]:
+                pl.wait(t)
 
-    run(2 * slots)
-    t0 = time.perf_counter()
-    run(frames)
-    wall = time.perf_counter() - t0
-    return {"frames": frames, "device_buffers": slots, "fps": round(frames / wall, 1),
+        run(2 * depth, 0)
+        t0 = time.perf_counter()
+        run(frames, 2 * depth)
+        wall = time.perf_counter() - t0
+    return {"frames": frames, "pipeline_depth": depth, "distinct_frames": distinct, "fps": round(frames / wall, 1),
             "ms_per_frame": round(wall * 1e3 / frames, 4), "mpix_s": round(frames * H * W / wall / 1e6, 1),
-            "transfer": "pinned host u8 HWC 1920x1080x3 in and out, H2D / D2H on two copy streams",
+            "transfer": "pinned host u8 HWC 1920x1080x3 in and out; upload, foveation and download on three "
+                        "streams of the library's host pipeline",
             "paper_context": "165 Hz on a GTX 1060 including transfers"}
 
 
@@ -508,6 +495,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic: 1920x1080 RGB u8 gratings + noise, %d-frame HBM pool, fixation uniform in central half" % args.pool,
+        "pool": {"frames": args.pool, "distinct_contents": args.distinct,
+                 "frames_touched_by_timed_steps": min(args.steps, args.pool),
+                 "bytes_touched_by_timed_steps": min(args.steps, args.pool) * H * W * C * 2},
         "config": {"workload": "1920x1080 RGB u8 -> u8, 32x32 fragments, sigma = 0.02*(e-64) capped at 16, "
                                "radius ceil(3 sigma), clamp-to-edge, one frame per launch",
                    "frame_pixels": H * W, "channels": C, "block": 32},

@@ -315,16 +315,23 @@ fov_status foveate_server_create(const fov_server_cfg* cfg, fov_server** out);
  * Queue one frame: in, out are single-frame views (n == 1) of the server's
  * dtype pair; p its parameters (block <= max_block, every fragment's sigma
  * <= max_sigma, at most max_fragments fragments).  The buffers (and a sigma
- * map, if any) must stay alive until poll reports the ticket done.  Returns
- * with *ticket without waiting for the GPU; when a stream is free and no frame
- * is queued, the frame's batch is launched from the calling thread before
- * returning (the server's device is made current for that and restored).
- * FOV_EAGAIN: request table full (poll and retry);
+ * map, if any) must stay alive until poll reports the ticket done.
+ *   ready : a hipEvent_t that the caller recorded on the stream that produces
+ *           `in` (and last used `out`), after that work; the frame's batch
+ *           waits for it on the device before reading `in`.  The server's
+ *           streams are not ordered after any caller stream, so without it
+ *           `in` must already be complete on the device when the frame is
+ *           submitted.  NULL = no wait.  The event must not be recorded again
+ *           before poll reports the ticket done.
+ * Returns with *ticket without waiting for the GPU; when a stream is free and
+ * no frame is queued, the frame's batch is launched from the calling thread
+ * before returning (the server's device is made current for that and
+ * restored).  FOV_EAGAIN: request table full (poll and retry);
  * FOV_ECLOSED: the server is being destroyed; FOV_EINVAL / FOV_ERANGE /
  * FOV_EDTYPE / FOV_EALIAS as for forward, or a frame larger than the budget.
  */
 fov_status foveate_submit(fov_server* s, const fov_tensor* in, const fov_tensor* out, const fov_params* p,
-                          uint64_t* ticket);
+                          void* ready, uint64_t* ticket);
 
 /*
  * *done = 1 once the frame's output is complete (then the ticket is retired
@@ -347,6 +354,53 @@ fov_status foveate_server_drain(fov_server* s);
 
 /* Finish all queued work, stop the scheduler, release everything. */
 fov_status foveate_server_destroy(fov_server* s);
+
+/* ---- host-to-host pipeline ------------------------------------------------------------------
+ *
+ * Frames that live in host memory: each is uploaded, foveated and downloaded
+ * (the per-frame loop of Alg. 1 moves the frame from pinned host memory to the
+ * GPU and the result back; Sec. 3 gives the transfer time beside the kernel
+ * time).  The upload of one frame, the foveation of the frame before it and
+ * the download of the one before that overlap: the pipeline owns `depth`
+ * device slots (one input and one output buffer each) and three streams
+ * (upload, foveation, download), and frame k uses slot k mod depth, ordered
+ * by events so that a slot is reused only after its previous frame has been
+ * read out of it.  Results are identical to foveate_forward's.
+ */
+typedef struct fov_pipeline fov_pipeline;
+
+/*
+ * Create a pipeline on the current device with `depth` slots (1..16) whose
+ * device buffers hold frames of up to max_in_bytes (input) and max_out_bytes
+ * (output).  The buffers and streams are allocated here.  FOV_EINVAL,
+ * FOV_ENOMEM, FOV_EHIP.
+ */
+fov_status foveate_pipeline_create(int32_t depth, size_t max_in_bytes, size_t max_out_bytes,
+                                   fov_pipeline** out);
+
+/*
+ * Queue one frame.  host_in, host_out: single-frame views (n == 1) of HOST
+ * memory, each dense (its elements fill one block from its first element, in
+ * any order of the dims: HWC and CHW frames alike), dtype pairs as forward,
+ * no overlap.  Pinned memory (hipHostMalloc, torch's pin_memory) lets the
+ * copies overlap with other work; pageable memory is accepted, its copies
+ * then hold the calling thread.  host_in must stay unchanged and host_out
+ * alive until the ticket is done.  Returns with *ticket once the frame's
+ * copies and kernels are queued.  FOV_EINVAL (also for a frame larger than
+ * the buffers), FOV_ELAYOUT (a view that is not dense), FOV_EDTYPE,
+ * FOV_EALIAS, FOV_ERANGE as for forward.
+ */
+fov_status foveate_pipeline_submit(fov_pipeline* pl, const fov_tensor* host_in, const fov_tensor* host_out,
+                                   const fov_params* p, uint64_t* ticket);
+
+/* *done = 1 once host_out holds the ticket's frame, else 0 (no wait).  FOV_ENOTICKET. */
+fov_status foveate_pipeline_query(fov_pipeline* pl, uint64_t ticket, int32_t* done);
+
+/* Block until host_out holds the ticket's frame, then retire the ticket.  FOV_ENOTICKET. */
+fov_status foveate_pipeline_wait(fov_pipeline* pl, uint64_t ticket);
+
+/* Finish all queued frames and release the pipeline's buffers and streams. */
+fov_status foveate_pipeline_destroy(fov_pipeline* pl);
 
 /*
  * Kernel timing for measurement.  Between foveate_profile_begin(capacity) and

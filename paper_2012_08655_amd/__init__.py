@@ -22,4 +22,10 @@ def __getattr__(name):
                 "tuning_clear", "tuning_count", "tuning_save", "tuning_load", "fragment_shift", "csf_params"):
         from . import api
         return getattr(api, name)
+    if name == "HostPipeline":
+        from .pipeline import HostPipeline
+        return HostPipeline
+    if name == "Server":
+        from .server import Server
+        return Server
     raise AttributeError(name)

@@ -77,10 +77,17 @@ SIGNATURES = {
     "foveate_now": (ctypes.c_double, []),
     "foveate_stream_timestamp": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "foveate_server_create": (ctypes.c_int, [ctypes.POINTER(FovServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
-    "foveate_submit": (ctypes.c_int, [ctypes.c_void_p, _TP, _TP, _PP, ctypes.POINTER(ctypes.c_uint64)]),
+    "foveate_submit": (ctypes.c_int, [ctypes.c_void_p, _TP, _TP, _PP, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_uint64)]),
     "foveate_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, _I32P, ctypes.POINTER(FovTiming)]),
     "foveate_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
     "foveate_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "foveate_pipeline_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_void_p)]),
+    "foveate_pipeline_submit": (ctypes.c_int, [ctypes.c_void_p, _TP, _TP, _PP, ctypes.POINTER(ctypes.c_uint64)]),
+    "foveate_pipeline_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, _I32P]),
+    "foveate_pipeline_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "foveate_pipeline_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "foveate_last_error": (ctypes.c_char_p, []),
     "foveate_version": (ctypes.c_char_p, []),
 }

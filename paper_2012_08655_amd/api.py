@@ -28,11 +28,14 @@ def _stream_handle(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def tensor_desc(t: torch.Tensor, layout: str) -> N.FovTensor:
-    """Describe a device tensor as (n, c, h, w) with element strides."""
+def tensor_desc(t: torch.Tensor, layout: str, host: bool = False) -> N.FovTensor:
+    """Describe a device tensor (or, with ``host``, a host tensor) as
+    (n, c, h, w) with element strides."""
     if t.dtype not in _DTYPES:
         raise TypeError("unsupported dtype %s" % t.dtype)
-    if not t.is_cuda:
+    if host and t.is_cuda:
+        raise ValueError("tensor must live in host memory")
+    if not host and not t.is_cuda:
         raise ValueError("tensor must live on the GPU")
     s = t.stride()
     if layout == "NCHW":

@@ -395,14 +395,12 @@ CallShape call_shape(const std::vector<FrameDesc>& frames) {
     return cs;
 }
 
-// One forward launch over a list of frames (any shapes, one dtype pair).  Up
-// to kArgFrames descriptors travel in the kernel arguments; more are uploaded
-// as a device table from pinned memory.
-fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream,
-                       const LaunchCfg* cfg_in, bool profile) {
+// Launch shape of one forward call over a list of frames (any shapes, one
+// dtype pair): counts, radius bound, LDS and scratch sizes; no device work.
+fov_status plan_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, const LaunchCfg* cfg_in,
+                        ForwardPlan* fp) {
     fov_status s;
     const int nf = (int)frames.size();
-    if (nf == 0) return FOV_OK;
     const CallShape cs = call_shape(frames);
     if (cs.r_cap >= kRadiusLimit)
         return set_error(FOV_ERANGE, "a fragment radius exceeds " + std::to_string(kRadiusLimit - 1) +
@@ -412,13 +410,13 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     const LaunchCfg cfg = cfg_in ? *cfg_in : select_cfg(frames, in_dtype, out_dtype, cs);
     const int L = cfg.split_log2;
     if ((cs.nfrag << (2 * L)) > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
-    std::vector<int32_t> prefix(nf + 1);
+    fp->prefix.assign(nf + 1, 0);
     int64_t total = 0;
     for (int i = 0; i < nf; ++i) {
-        prefix[i] = (int32_t)total;
+        fp->prefix[i] = (int32_t)total;
         total += (int64_t)frames[i].p.nbx * frames[i].nby;
     }
-    prefix[nf] = (int32_t)total;
+    fp->prefix[nf] = (int32_t)total;
     const int r_cap = cs.r_cap;
     const int tile = (cs.bmax + (1 << L) - 1) >> L;
     const int sr = cfg.strip_rows;
@@ -438,7 +436,7 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
         return set_error(FOV_ERANGE, "radius " + std::to_string(r_cap) + " needs " + std::to_string(lds) +
                                          " bytes of LDS; the device allows " + std::to_string(dev->lds_limit));
     const int wsize = in_dtype == FOV_F64 ? 8 : 4;
-    FwdLaunch a;
+    FwdLaunch& a = fp->a;
     std::memset(&a, 0, sizeof(a));
     a.nframes = nf;
     a.nfrag = (int32_t)total;
@@ -454,15 +452,27 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     a.cs_rmax = cs_rmax;
     a.cmax = cs.c;
     a.nslots = cs_rmax >= 0 ? queue_slots_by_channel(a.nfrag, r_cap, cs.c) : queue_slots(a.nfrag << (2 * L), r_cap);
-    const size_t pbytes = (plan_bytes(a.nfrag, a.nslots, a.wstride, wsize) + 255) / 256 * 256;
-    const bool upload = nf > kArgFrames;
-    const size_t tbytes = frame_table_bytes(nf);
-    Workspace* ws = nullptr;
-    std::unique_lock<std::mutex> hold;
-    if ((s = workspace(stream, pbytes + tbytes, upload ? tbytes : 0, &ws, &hold)) != FOV_OK) return s;
-    const PlanBuffers plan = carve_plan(ws->dev, a.nfrag, a.nslots);
-    if ((s = stage_frame_table(frames.data(), nf, prefix.data(), ws, static_cast<char*>(ws->dev) + pbytes, tbytes,
-                               stream, &a)) != FOV_OK)
+    fp->lds = lds;
+    fp->persistent = cfg.persistent;
+    fp->pbytes = (plan_bytes(a.nfrag, a.nslots, a.wstride, wsize) + 255) / 256 * 256;
+    fp->tbytes = frame_table_bytes(nf);
+    fp->lds_limit = dev->lds_limit;
+    fp->cus = dev->cus;
+    return FOV_OK;
+}
+
+// Plan, order and main kernels of a planned call, with its plan workspace at
+// `scratch` (at least fp.pbytes + fp.tbytes bytes of device memory).  Frame
+// tables of more than kArgFrames frames are uploaded from ws's pinned buffer
+// (ws may be NULL for calls of at most kArgFrames frames).
+fov_status launch_planned(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, ForwardPlan& fp,
+                          void* scratch, Workspace* ws, hipStream_t stream, bool profile) {
+    fov_status s;
+    FwdLaunch& a = fp.a;
+    const int nf = (int)frames.size();
+    const PlanBuffers plan = carve_plan(scratch, a.nfrag, a.nslots);
+    if ((s = stage_frame_table(frames.data(), nf, fp.prefix.data(), ws, static_cast<char*>(scratch) + fp.pbytes,
+                               fp.tbytes, stream, &a)) != FOV_OK)
         return s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile && g_prof.on && g_prof.calls++ % g_prof.every == 0 && g_prof.used < g_prof.ev.size()) {
@@ -470,8 +480,24 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
         e1 = g_prof.ev[g_prof.used].second;
         ++g_prof.used;
     }
-    return launch_forward(a, in_dtype, out_dtype, lds, plan, stream, dev->lds_limit, dev->cus, cfg.persistent, e0,
-                          e1);
+    return launch_forward(a, in_dtype, out_dtype, fp.lds, plan, stream, fp.lds_limit, fp.cus, fp.persistent, e0, e1);
+}
+
+// One forward launch over a list of frames (any shapes, one dtype pair), its
+// plan workspace in the library's per-(device, stream) workspace.  Up to
+// kArgFrames descriptors travel in the kernel arguments; more are uploaded
+// as a device table from pinned memory.
+fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream,
+                       const LaunchCfg* cfg_in, bool profile) {
+    if (frames.empty()) return FOV_OK;
+    fov_status s;
+    ForwardPlan fp;
+    if ((s = plan_forward(frames, in_dtype, out_dtype, cfg_in, &fp)) != FOV_OK) return s;
+    const bool upload = (int)frames.size() > kArgFrames;
+    Workspace* ws = nullptr;
+    std::unique_lock<std::mutex> hold;
+    if ((s = workspace(stream, fp.pbytes + fp.tbytes, upload ? fp.tbytes : 0, &ws, &hold)) != FOV_OK) return s;
+    return launch_planned(frames, in_dtype, out_dtype, fp, ws->dev, ws, stream, profile);
 }
 
 // Scratch of the adjoint's horizontal transposes, per launch: frames are

@@ -88,4 +88,21 @@ fov_status collect_batch(const fov_tensor* ins, const fov_tensor* outs, const fo
 fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, hipStream_t stream,
                        const LaunchCfg* cfg = nullptr, bool profile = true);
 
+// The launch shape of one forward call (run_forward in two steps, for callers
+// that bring their own plan workspace).
+struct ForwardPlan {
+    FwdLaunch a;                  // counts and sizes; the frame table is placed by launch_planned
+    std::vector<int32_t> prefix;  // first fragment of each frame, nframes + 1 entries
+    size_t lds = 0;               // dynamic LDS per workgroup
+    size_t pbytes = 0;            // plan workspace bytes (radii, order keys, queue, taps)
+    size_t tbytes = 0;            // frame table bytes, placed after the plan workspace
+    size_t lds_limit = 0;
+    int cus = 0;
+    bool persistent = false;
+};
+fov_status plan_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, const LaunchCfg* cfg,
+                        ForwardPlan* fp);
+fov_status launch_planned(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, ForwardPlan& fp,
+                          void* scratch, Workspace* ws, hipStream_t stream, bool profile);
+
 }  // namespace fov

@@ -36,6 +36,7 @@ double now_s() {
 struct Req {
     fov_tensor in, out;
     fov_params p;
+    hipEvent_t ready = nullptr;  // the caller's producer event (NULL: input already complete)
     size_t bytes = 0;
     int nfrag = 0;
     bool done = false;
@@ -246,12 +247,18 @@ fov_status build_graph(ServerImpl* s, Slot& sl) {
 }
 
 // Launch a batch on a slot; on failure the caller completes it with the error.
-fov_status launch_batch(ServerImpl* s, Slot& sl, const std::vector<FrameDesc>& frames, int nfrag) {
+// `ready` holds the producer events of the batch's frames that have one.
+fov_status launch_batch(ServerImpl* s, Slot& sl, const std::vector<FrameDesc>& frames, int nfrag,
+                        const std::vector<hipEvent_t>& ready) {
     if (s->fake_mode()) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->fake_q.push_back({now_s() + s->cfg.test_fake_device_us * 1e-6, &sl});
         s->fake_cv.notify_all();
         return FOV_OK;
+    }
+    for (hipEvent_t ev : ready) {
+        hipError_t e = hipStreamWaitEvent(sl.run, ev, 0);
+        if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent(ready)");
     }
     if (s->cfg.use_graph) {
         char* h = static_cast<char*>(sl.host);
@@ -301,6 +308,7 @@ bool dispatch_once(ServerImpl* s, std::unique_lock<std::mutex>& lk) {
     if (!free_slot || s->admitted.empty()) return false;
     std::vector<uint64_t> ids;
     std::vector<FrameDesc> frames;
+    std::vector<hipEvent_t> ready;
     int nfrag = 0;
     size_t bytes = 0;
     while (!s->admitted.empty() && (int)ids.size() < s->cfg.max_batch_frames) {
@@ -308,6 +316,7 @@ bool dispatch_once(ServerImpl* s, std::unique_lock<std::mutex>& lk) {
         if (!ids.empty() && nfrag + r.nfrag > s->cfg.max_fragments) break;
         ids.push_back(s->admitted.front());
         frames.push_back(make_frame_desc(r.in, r.out, 0, r.p));
+        if (r.ready) ready.push_back(r.ready);
         nfrag += r.nfrag;
         bytes += r.bytes;
         s->admitted.pop_front();
@@ -325,7 +334,7 @@ bool dispatch_once(ServerImpl* s, std::unique_lock<std::mutex>& lk) {
     free_slot->status =
         (s->cfg.test_fail_every > 0 && s->batches % (uint64_t)s->cfg.test_fail_every == 0) ? FOV_EHIP : FOV_OK;
     lk.unlock();
-    const fov_status st = launch_batch(s, *free_slot, frames, nfrag);
+    const fov_status st = launch_batch(s, *free_slot, frames, nfrag, ready);
     if (st != FOV_OK) {
         free_slot->status = st;
         on_batch_done(free_slot);
@@ -434,7 +443,7 @@ fov_status foveate_server_create(const fov_server_cfg* cfg, fov_server** out) {
 }
 
 fov_status foveate_submit(fov_server* srv, const fov_tensor* in, const fov_tensor* out, const fov_params* p,
-                          uint64_t* ticket) {
+                          void* ready, uint64_t* ticket) {
     if (!srv || !ticket) return set_error(FOV_EINVAL, "NULL argument");
     ServerImpl* s = srv->impl;
     bool empty = false;
@@ -446,6 +455,7 @@ fov_status foveate_submit(fov_server* srv, const fov_tensor* in, const fov_tenso
     r.in = *in;
     r.out = *out;
     r.p = *p;
+    r.ready = static_cast<hipEvent_t>(ready);
     if (!empty) {
         if (in->n != 1) return set_error(FOV_EINVAL, "a request holds one frame (n == 1)");
         if (p->block > s->cfg.max_block) return set_error(FOV_EINVAL, "block exceeds the server's max_block");

@@ -47,19 +47,35 @@ class Server:
         N.check(N.lib().foveate_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self._keep: dict[int, tuple] = {}
+        self._events: dict[int, object] = {}  # ticket -> producer event (until polled done)
+        self._free_events: list = []
 
-    def submit_desc(self, din: N.FovTensor, dout: N.FovTensor, params: N.FovParams, keep=()) -> int:
+    def submit_desc(self, din: N.FovTensor, dout: N.FovTensor, params: N.FovParams, keep=(), ready=None) -> int:
+        """Queue a frame given as descriptors; ``ready`` is a raw hipEvent_t
+        handle (int) the frame's batch waits for, or None."""
         t = ctypes.c_uint64()
         N.check(N.lib().foveate_submit(self._h, ctypes.byref(din), ctypes.byref(dout), ctypes.byref(params),
-                                       ctypes.byref(t)))
+                                       ctypes.c_void_p(ready) if ready else None, ctypes.byref(t)))
         self._keep[t.value] = keep
         return t.value
 
-    def submit(self, x, out, params, layout: str = "HWC") -> int:
+    def submit(self, x, out, params, layout: str = "HWC", stream=None) -> int:
+        """Queue frame ``x`` into ``out``.  The frame's batch waits on the
+        device for the work queued so far on ``stream`` (default: torch's
+        current stream), where ``x`` was produced and ``out`` last used."""
+        import torch
         from . import api
         din, dout = api.tensor_desc(x, layout), api.tensor_desc(out, layout)
         arr, _, k = api._params_array(params, 1)
-        return self.submit_desc(din, dout, arr[0], keep=(x, out, k))
+        ev = self._free_events.pop() if self._free_events else torch.cuda.Event()
+        ev.record(stream if stream is not None else torch.cuda.current_stream())
+        try:
+            tk = self.submit_desc(din, dout, arr[0], keep=(x, out, k), ready=ev.cuda_event)
+        except Exception:
+            self._free_events.append(ev)
+            raise
+        self._events[tk] = ev
+        return tk
 
     def poll(self, ticket: int):
         """(done, Timing or None).  Raises FoveateError if the frame failed."""
@@ -68,6 +84,9 @@ class Server:
         st = N.lib().foveate_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(tm))
         if done.value:
             self._keep.pop(ticket, None)
+            ev = self._events.pop(ticket, None)
+            if ev is not None:
+                self._free_events.append(ev)  # the batch has waited for it: free to record again
         N.check(st)
         if not done.value:
             return False, None
@@ -81,6 +100,8 @@ class Server:
             N.check(N.lib().foveate_server_destroy(self._h))
             self._h = None
             self._keep.clear()
+            self._events.clear()
+            self._free_events.clear()
 
     def __enter__(self):
         return self

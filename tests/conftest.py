@@ -34,3 +34,25 @@ def fov(dev):
     import paper_2012_08655_amd as fov
     fov.load()
     return fov
+
+
+@pytest.fixture(scope="session")
+def batch64():
+    """The 64-frame mixed-resolution batch (resolutions uniform over 640x480 ..
+    3840x2160, gratings + noise, central-half fixation, slope in [0.01, 0.04],
+    cap 16, e0 64) and the index of its first 4K frame."""
+    import synth
+    frames, params = synth.batch_mixed(64, seed=3, unique_content=2)
+    i4k = next(i for i, f in enumerate(frames) if f.shape[:2] == (2160, 3840))
+    return frames, params, i4k
+
+
+@pytest.fixture(scope="session")
+def oracle_4k(orc, batch64):
+    """FP64 oracle of that batch's first 4K frame, u8 HWC (computed once per
+    session: about half a minute on 16 cores)."""
+    import numpy as np
+    frames, params, i4k = batch64
+    ref = orc.forward(frames[i4k].transpose(2, 0, 1).astype(np.float64), params[i4k])
+    return orc.to_u8(ref).transpose(1, 2, 0)
+

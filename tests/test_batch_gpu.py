@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import synth
+from parity import assert_u8_close
 
 pytestmark = pytest.mark.gpu
 
@@ -67,14 +68,16 @@ def test_batch_rejects_mixed_dtypes_and_overlap(fov, dev):
     assert ei.value.status == -4
 
 
-def test_mixed_resolution_batch_of_64(fov, orc, dev):
+def test_mixed_resolution_batch_of_64(fov, orc, dev, batch64, oracle_4k):
     # 64 frames, resolution uniform over {640x480, 1280x720, 1920x1080,
     # 3840x2160}, gratings + noise, fixation uniform in the central half,
     # slope uniform in [0.01, 0.04], cap 16, e0 64 px.
-    frames, params = synth.batch_mixed(64, seed=3, unique_content=2)
+    frames, params, i4k = batch64
     ins = [torch.from_numpy(f).to(dev) for f in frames]
     outs = fov.forward_batch(ins, params, layout="HWC")
     torch.cuda.synchronize()
+    # a whole 4K frame of the mix, element by element against the oracle
+    assert_u8_close(outs[i4k].cpu().numpy(), oracle_4k, "4K frame %d in the batch" % i4k)
     rng = np.random.default_rng(0)
     checked = set()
     for i in range(64):

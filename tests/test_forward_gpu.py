@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import synth
+from parity import assert_f32_close, assert_u8_close
 
 pytestmark = pytest.mark.gpu
 
@@ -131,6 +132,26 @@ def test_cfg2_full_size_sampled(fov, orc, dev, fix):
     assert np.max(np.abs(got8 - orc.to_u8(ref).astype(np.int32))) <= 1
     # u8 output equals the rounded f32 output of the same kernel
     assert np.array_equal(y8.cpu().numpy(), np.clip(np.rint(yf.cpu().numpy()), 0, 255).astype(np.uint8))
+
+
+@pytest.mark.parametrize("fix", ["centre", "rand0"])
+def test_cfg2_full_frame(fov, orc, dev, fix):
+    # Every pixel of a 1920x1080 RGB u8 frame (32 px fragments, sigma = 0.02 (e - 64) capped
+    # at 16) against the oracle: u8 out within 1 LSB, u8 -> f32 out within 2e-5 on [0,1]
+    # (2e-5 * 255 raw).  The u8 -> u8 call runs in the launch configuration the autotuner
+    # picks for this workload, as the benchmark's timed loop does.
+    fr = synth.grating_frame(1080, 1920, 3, seed=1)
+    rng = np.random.default_rng({"centre": 0, "rand0": 7}[fix])
+    p = synth.params_cfg2(rng, centred=(fix == "centre"))
+    t = torch.from_numpy(fr).to(dev)
+    y8 = torch.empty_like(t)
+    fov.autotune(t, p, out=y8, layout="HWC", reps=2)
+    fov.forward(t, p, out=y8, layout="HWC")
+    yf = fov.forward(t, p, layout="HWC", out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    ref = orc.forward(fr.transpose(2, 0, 1).astype(np.float64), p).transpose(1, 2, 0)
+    assert_f32_close(yf.cpu().numpy(), ref, TOL_F32 * 255, "1080p u8->f32 " + fix)
+    assert_u8_close(y8.cpu().numpy(), orc.to_u8(ref), "1080p u8->u8 " + fix)
 
 
 def test_identity_and_constant_u8_exact(fov, dev):
