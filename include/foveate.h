@@ -180,6 +180,28 @@ fov_status foveate_forward_batch(const fov_tensor* ins, const fov_tensor* outs, 
                                  int32_t nframes, void* stream);
 
 /*
+ * foveate_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and bitwise the same outputs as foveate_forward,
+ * but the plan workspace is a fixed 16 MiB array of device memory that the
+ * library's code object holds on every GPU it runs on until the process ends;
+ * the call makes no hipMalloc, hipFree, pinned or other allocation.  Limits:
+ *   - at most 16 frames per call (n <= 16; their descriptors travel in the
+ *     kernel arguments), else FOV_EINVAL;
+ *   - the call's plan workspace (per fragment about 4 * (2r_max + 1) bytes of
+ *     taps plus a few words of queue) must fit the 16 MiB, else FOV_EINVAL
+ *     with the size it needed; a 3840x2160 frame in 32 px fragments fits at
+ *     every radius the on-chip memory allows.
+ * Every call on one GPU uses that GPU's single array: calls that overlap on
+ * the device (different streams, or host threads without ordering) race and
+ * may produce wrong outputs; order them on one stream.  Nothing the array
+ * keeps from an earlier call is read before it is rewritten.  The first call
+ * on each device looks the array's device address up (hipGetSymbolAddress).
+ */
+fov_status foveate_forward_noalloc(const fov_tensor* in, const fov_tensor* out, const fov_params* p,
+                                   int32_t np, void* stream);
+
+/*
  * Adjoint (transpose) of foveate_forward for the same parameters:
  * grad_in = A_p^T grad_out, computed as a gather (each workgroup owns a tile
  * of grad_in and visits every fragment whose window reaches it; no atomics).

@@ -61,6 +61,7 @@ SIGNATURES = {
     "foveate_plan_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _PP, ctypes.c_void_p, ctypes.c_void_p]),
     "foveate_forward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
     "foveate_forward_batch": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
+    "foveate_forward_noalloc": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
     "foveate_backward": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_void_p]),
     "foveate_autotune": (ctypes.c_int, [_TP, _TP, _PP, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.POINTER(FovTuning)]),

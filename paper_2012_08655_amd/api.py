@@ -97,6 +97,16 @@ def forward(x: torch.Tensor, params, out: torch.Tensor | None = None, layout: st
     return out
 
 
+def forward_noalloc(x: torch.Tensor, params, out: torch.Tensor, layout: str = "NCHW", stream=None) -> torch.Tensor:
+    """``forward`` through the library's allocation-free entry point: the
+    plan workspace is the library's fixed device array, so ``out`` must be
+    given (at most 16 frames per call; calls on one GPU must not overlap)."""
+    di, do = tensor_desc(x, layout), tensor_desc(out, layout)
+    arr, npar, _keep = _params_array(params, di.n)
+    N.check(N.lib().foveate_forward_noalloc(ctypes.byref(di), ctypes.byref(do), arr, npar, _stream_handle(stream)))
+    return out
+
+
 def forward_batch(frames, params, outs=None, layout: str = "HWC", out_dtype: torch.dtype | None = None,
                   stream=None):
     """Foveate a list of frames of possibly different sizes in one launch.

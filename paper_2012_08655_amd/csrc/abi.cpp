@@ -384,9 +384,10 @@ fov_status stage_frame_table(const FrameDesc* frames, int nf, const int32_t* pre
     return FOV_OK;
 }
 
-CallShape call_shape(const std::vector<FrameDesc>& frames) {
+CallShape call_shape(const FrameDesc* frames, int nf) {
     CallShape cs;
-    for (const FrameDesc& f : frames) {
+    for (int i = 0; i < nf; ++i) {
+        const FrameDesc& f = frames[i];
         cs.nfrag += (int64_t)f.p.nbx * f.nby;
         cs.r_cap = std::max(cs.r_cap, frame_r_max(f.p, f.h));
         cs.bmax = std::max(cs.bmax, f.p.block);
@@ -397,26 +398,18 @@ CallShape call_shape(const std::vector<FrameDesc>& frames) {
 
 // Launch shape of one forward call over a list of frames (any shapes, one
 // dtype pair): counts, radius bound, LDS and scratch sizes; no device work.
-fov_status plan_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, const LaunchCfg* cfg_in,
+fov_status plan_forward(const FrameDesc* frames, int nf, int in_dtype, int out_dtype, const LaunchCfg* cfg_in,
                         ForwardPlan* fp) {
     fov_status s;
-    const int nf = (int)frames.size();
-    const CallShape cs = call_shape(frames);
+    const CallShape cs = call_shape(frames, nf);
     if (cs.r_cap >= kRadiusLimit)
         return set_error(FOV_ERANGE, "a fragment radius exceeds " + std::to_string(kRadiusLimit - 1) +
                                          " pixels; no workgroup can stage its window");
     const DeviceInfo* dev = nullptr;
     if ((s = device_info(&dev)) != FOV_OK) return s;
-    const LaunchCfg cfg = cfg_in ? *cfg_in : select_cfg(frames, in_dtype, out_dtype, cs);
+    const LaunchCfg cfg = cfg_in ? *cfg_in : select_cfg(nf, in_dtype, out_dtype, cs);
     const int L = cfg.split_log2;
     if ((cs.nfrag << (2 * L)) > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
-    fp->prefix.assign(nf + 1, 0);
-    int64_t total = 0;
-    for (int i = 0; i < nf; ++i) {
-        fp->prefix[i] = (int32_t)total;
-        total += (int64_t)frames[i].p.nbx * frames[i].nby;
-    }
-    fp->prefix[nf] = (int32_t)total;
     const int r_cap = cs.r_cap;
     const int tile = (cs.bmax + (1 << L) - 1) >> L;
     const int sr = cfg.strip_rows;
@@ -438,6 +431,16 @@ fov_status plan_forward(const std::vector<FrameDesc>& frames, int in_dtype, int 
     const int wsize = in_dtype == FOV_F64 ? 8 : 4;
     FwdLaunch& a = fp->a;
     std::memset(&a, 0, sizeof(a));
+    // first fragment of each frame: in the kernel arguments' copy for calls of at most kArgFrames
+    // frames (no host allocation), else in the table that launch_planned uploads
+    if (nf > kArgFrames) fp->prefix_table.assign(nf + 1, 0);
+    int32_t* prefix = nf > kArgFrames ? fp->prefix_table.data() : a.kprefix;
+    int64_t total = 0;
+    for (int i = 0; i < nf; ++i) {
+        prefix[i] = (int32_t)total;
+        total += (int64_t)frames[i].p.nbx * frames[i].nby;
+    }
+    prefix[nf] = (int32_t)total;
     a.nframes = nf;
     a.nfrag = (int32_t)total;
     a.split_log2 = L;
@@ -465,13 +468,12 @@ fov_status plan_forward(const std::vector<FrameDesc>& frames, int in_dtype, int 
 // `scratch` (at least fp.pbytes + fp.tbytes bytes of device memory).  Frame
 // tables of more than kArgFrames frames are uploaded from ws's pinned buffer
 // (ws may be NULL for calls of at most kArgFrames frames).
-fov_status launch_planned(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, ForwardPlan& fp,
+fov_status launch_planned(const FrameDesc* frames, int nf, int in_dtype, int out_dtype, ForwardPlan& fp,
                           void* scratch, Workspace* ws, hipStream_t stream, bool profile) {
     fov_status s;
     FwdLaunch& a = fp.a;
-    const int nf = (int)frames.size();
     const PlanBuffers plan = carve_plan(scratch, a.nfrag, a.nslots);
-    if ((s = stage_frame_table(frames.data(), nf, fp.prefix.data(), ws, static_cast<char*>(scratch) + fp.pbytes,
+    if ((s = stage_frame_table(frames, nf, fp.prefix(), ws, static_cast<char*>(scratch) + fp.pbytes,
                                fp.tbytes, stream, &a)) != FOV_OK)
         return s;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -492,12 +494,12 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
     if (frames.empty()) return FOV_OK;
     fov_status s;
     ForwardPlan fp;
-    if ((s = plan_forward(frames, in_dtype, out_dtype, cfg_in, &fp)) != FOV_OK) return s;
+    if ((s = plan_forward(frames.data(), (int)frames.size(), in_dtype, out_dtype, cfg_in, &fp)) != FOV_OK) return s;
     const bool upload = (int)frames.size() > kArgFrames;
     Workspace* ws = nullptr;
     std::unique_lock<std::mutex> hold;
     if ((s = workspace(stream, fp.pbytes + fp.tbytes, upload ? fp.tbytes : 0, &ws, &hold)) != FOV_OK) return s;
-    return launch_planned(frames, in_dtype, out_dtype, fp, ws->dev, ws, stream, profile);
+    return launch_planned(frames.data(), (int)frames.size(), in_dtype, out_dtype, fp, ws->dev, ws, stream, profile);
 }
 
 // Scratch of the adjoint's horizontal transposes, per launch: frames are
@@ -509,15 +511,14 @@ fov_status run_backward_group(const FrameDesc* frames, int nf, int dtype, hipStr
     fov_status s;
     const DeviceInfo* dev = nullptr;
     if ((s = device_info(&dev)) != FOV_OK) return s;
-    const std::vector<FrameDesc> fl(frames, frames + nf);
-    const CallShape cs = call_shape(fl);
+    const CallShape cs = call_shape(frames, nf);
     const int es = dtype == FOV_F64 ? 8 : 4;
     const AdjShape sh = adjoint_shape(es, cs.r_cap, cs.bmax, cs.c);
     std::vector<int32_t> prefix(nf + 1);
     int64_t total = 0;
     for (int i = 0; i < nf; ++i) {
         prefix[i] = (int32_t)total;
-        total += (int64_t)fl[i].p.nbx * fl[i].nby;
+        total += (int64_t)frames[i].p.nbx * frames[i].nby;
     }
     prefix[nf] = (int32_t)total;
     if (total > ((int64_t)1 << 30)) return set_error(FOV_EINVAL, "too many fragments in one call");
@@ -545,7 +546,7 @@ fov_status run_backward_group(const FrameDesc* frames, int nf, int dtype, hipStr
     plan.weights = wbase + (size_t)kAdjWeightLead * es;
     char* dtab = wbase + wbytes;
     void* scratch = dtab + tbytes;
-    if ((s = stage_frame_table(fl.data(), nf, prefix.data(), ws, dtab, tbytes, stream, &a)) != FOV_OK) return s;
+    if ((s = stage_frame_table(frames, nf, prefix.data(), ws, dtab, tbytes, stream, &a)) != FOV_OK) return s;
     return launch_adjoint(a, sh, es, plan, wbase, scratch, stream, dev->lds_limit);
 }
 
@@ -554,16 +555,16 @@ fov_status run_backward(const fov_tensor* go, const fov_tensor* gi, const fov_pa
     std::vector<FrameDesc> frames;
     frames.reserve(go->n);
     for (int i = 0; i < go->n; ++i) frames.push_back(make_frame_desc(*go, *gi, i, p[np == 1 ? 0 : i]));
-    if (call_shape(frames).r_cap >= kRadiusLimit)
+    if (call_shape(frames.data(), (int)frames.size()).r_cap >= kRadiusLimit)
         return set_error(FOV_ERANGE, "a fragment radius exceeds " + std::to_string(kRadiusLimit - 1) +
                                          " pixels; no workgroup can stage its window");
     const int es = go->dtype == FOV_F64 ? 8 : 4;
     size_t f0 = 0;
     while (f0 < frames.size()) {
         size_t f1 = f0 + 1;
-        CallShape cs = call_shape({frames[f0]});
+        CallShape cs = call_shape(&frames[f0], 1);
         while (f1 < frames.size()) {
-            const CallShape one = call_shape({frames[f1]});
+            const CallShape one = call_shape(&frames[f1], 1);
             CallShape m = cs;
             m.r_cap = std::max(m.r_cap, one.r_cap);
             m.bmax = std::max(m.bmax, one.bmax);

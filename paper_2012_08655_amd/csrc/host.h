@@ -65,11 +65,11 @@ struct CallShape {
     int r_cap = 0, bmax = 1, c = 1;
     int64_t nfrag = 0;
 };
-CallShape call_shape(const std::vector<FrameDesc>& frames);
+CallShape call_shape(const FrameDesc* frames, int nf);
 
 // Configuration for a call: the thread's forced one, else the tuning cache's
 // entry for the call's class, else the defaults.
-LaunchCfg select_cfg(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, const CallShape& cs);
+LaunchCfg select_cfg(int nframes, int in_dtype, int out_dtype, const CallShape& cs);
 
 // Validation of a forward (or backward) call's views and parameters.
 fov_status prepare(const fov_tensor* in, const fov_tensor* out, const fov_params* p, int32_t np, bool backward,
@@ -91,8 +91,10 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
 // The launch shape of one forward call (run_forward in two steps, for callers
 // that bring their own plan workspace).
 struct ForwardPlan {
-    FwdLaunch a;                  // counts and sizes; the frame table is placed by launch_planned
-    std::vector<int32_t> prefix;  // first fragment of each frame, nframes + 1 entries
+    FwdLaunch a;                        // counts and sizes; the frame table is placed by launch_planned
+    std::vector<int32_t> prefix_table;  // first fragment of each frame (nframes + 1 entries) when
+                                        // nframes > kArgFrames; otherwise they are in a.kprefix
+    const int32_t* prefix() const { return a.nframes > kArgFrames ? prefix_table.data() : a.kprefix; }
     size_t lds = 0;               // dynamic LDS per workgroup
     size_t pbytes = 0;            // plan workspace bytes (radii, order keys, queue, taps)
     size_t tbytes = 0;            // frame table bytes, placed after the plan workspace
@@ -100,9 +102,9 @@ struct ForwardPlan {
     int cus = 0;
     bool persistent = false;
 };
-fov_status plan_forward(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, const LaunchCfg* cfg,
+fov_status plan_forward(const FrameDesc* frames, int nf, int in_dtype, int out_dtype, const LaunchCfg* cfg,
                         ForwardPlan* fp);
-fov_status launch_planned(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, ForwardPlan& fp,
+fov_status launch_planned(const FrameDesc* frames, int nf, int in_dtype, int out_dtype, ForwardPlan& fp,
                           void* scratch, Workspace* ws, hipStream_t stream, bool profile);
 
 }  // namespace fov

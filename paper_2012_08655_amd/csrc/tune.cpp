@@ -156,7 +156,7 @@ fov_status autotune_frames(const std::vector<FrameDesc>& frames, int in_dtype, i
     if (s != FOV_OK) return s;
     if (reps < 0 || reps > 1000) return set_error(FOV_EINVAL, "reps must be in 0..1000");
     if (reps == 0) reps = 5;
-    const CallShape cs = call_shape(frames);
+    const CallShape cs = call_shape(frames.data(), (int)frames.size());
     const std::vector<LaunchCfg> cands = candidates(*dev, in_dtype, cs);
     if (cands.empty()) {
         // no configuration fits: let a plain call report the LDS error
@@ -227,11 +227,11 @@ constexpr const char* kTag = "fov-tune-v3";
 
 }  // namespace
 
-LaunchCfg select_cfg(const std::vector<FrameDesc>& frames, int in_dtype, int out_dtype, const CallShape& cs) {
+LaunchCfg select_cfg(int nframes, int in_dtype, int out_dtype, const CallShape& cs) {
     if (g_forced_on) return g_forced;
     const DeviceInfo* dev = nullptr;
     if (device_info(&dev) == FOV_OK) {
-        const TuneKey k = make_key(*dev, (int)frames.size(), in_dtype, out_dtype, cs);
+        const TuneKey k = make_key(*dev, nframes, in_dtype, out_dtype, cs);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(k);
         if (it != g_tune.end()) return it->second.cfg;
