@@ -43,6 +43,13 @@ __host__ __device__ inline int inter_pitch(int TH, int es) {
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
+// LDS bytes of a forward workgroup's taps for radii up to r_cap: all 2r+1 taps (for the vertical
+// and the plain horizontal pass), then w_1 .. w_r again from a 16-byte boundary (for the
+// symmetric pass), each list padded to whole 4-tap groups.
+__host__ __device__ inline size_t tap_lds_bytes(int r_cap, int ec) {
+    return align16((size_t)(round_up(2 * r_cap + 1, 4) + round_up(r_cap, 4) + 4) * ec);
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Index of the calling wavefront in its workgroup, as a scalar (uniform) value.
@@ -199,13 +206,14 @@ __device__ __forceinline__ void sym_part(int nt, float (&acc)[kPH], uint2 L0, ui
 }
 
 // 8 horizontal outputs, radius r >= 1.  rc points at the centre of output 0 (8-byte aligned);
-// wc[k] = w_k for k = 0..r.  Reads samples rc[-r-3 .. r+10]: the ones outside [-r, r+7] fall in
-// halves whose sums no output uses.  Sums are taken in the order k = 0, 1, .., r.
-__device__ __forceinline__ void hconv_sym(float (&acc)[kPH], const _Float16* rc, int r, const float* __restrict__ wc) {
+// w0 = w_0 and ws[j] = w_{j+1} for j = 0..r-1 (16-byte aligned).  Reads samples rc[-r-3 .. r+10]:
+// the ones outside [-r, r+7] fall in halves whose sums no output uses.  Sums are taken in the
+// order k = 0, 1, .., r.
+__device__ __forceinline__ void hconv_sym(float (&acc)[kPH], const _Float16* rc, int r, float w0,
+                                          const float* __restrict__ ws) {
     uint2 LA = load_grp(rc), LB = load_grp(rc + 4), LC;
     uint2 RA = LA, RB = LB, RC;
     {
-        const float w0 = wc[0];
         const uint32_t x[4] = {LA.x, LA.y, LB.x, LB.y};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -220,30 +228,30 @@ __device__ __forceinline__ void hconv_sym(float (&acc)[kPH], const _Float16* rc,
     for (; m + 3 <= M; m += 3) {
         LC = load_grp(rc - 4 * (m + 1));
         RC = load_grp(rc + 4 * (m + 2));
-        sym_block<4>(acc, LC, LA, LB, RA, RB, RC, wc + 4 * m + 1);
+        sym_block<4>(acc, LC, LA, LB, RA, RB, RC, ws + 4 * m);
         LB = load_grp(rc - 4 * (m + 2));
         RA = load_grp(rc + 4 * (m + 3));
-        sym_block<4>(acc, LB, LC, LA, RB, RC, RA, wc + 4 * m + 5);
+        sym_block<4>(acc, LB, LC, LA, RB, RC, RA, ws + 4 * m + 4);
         LA = load_grp(rc - 4 * (m + 3));
         RB = load_grp(rc + 4 * (m + 4));
-        sym_block<4>(acc, LA, LB, LC, RC, RA, RB, wc + 4 * m + 9);
+        sym_block<4>(acc, LA, LB, LC, RC, RA, RB, ws + 4 * m + 8);
     }
     if (m == M && NT == 0) return;
     LC = load_grp(rc - 4 * (m + 1));
     RC = load_grp(rc + 4 * (m + 2));
-    if (m == M) { sym_part(NT, acc, LC, LA, LB, RA, RB, RC, wc + 4 * m + 1); return; }
-    sym_block<4>(acc, LC, LA, LB, RA, RB, RC, wc + 4 * m + 1);
+    if (m == M) { sym_part(NT, acc, LC, LA, LB, RA, RB, RC, ws + 4 * m); return; }
+    sym_block<4>(acc, LC, LA, LB, RA, RB, RC, ws + 4 * m);
     ++m;
     if (m == M && NT == 0) return;
     LB = load_grp(rc - 4 * (m + 1));
     RA = load_grp(rc + 4 * (m + 2));
-    if (m == M) { sym_part(NT, acc, LB, LC, LA, RB, RC, RA, wc + 4 * m + 1); return; }
-    sym_block<4>(acc, LB, LC, LA, RB, RC, RA, wc + 4 * m + 1);
+    if (m == M) { sym_part(NT, acc, LB, LC, LA, RB, RC, RA, ws + 4 * m); return; }
+    sym_block<4>(acc, LB, LC, LA, RB, RC, RA, ws + 4 * m);
     ++m;
     if (NT == 0) return;  // m == M here
     LA = load_grp(rc - 4 * (m + 1));
     RB = load_grp(rc + 4 * (m + 2));
-    sym_part(NT, acc, LA, LB, LC, RC, RA, RB, wc + 4 * m + 1);
+    sym_part(NT, acc, LA, LB, LC, RC, RA, RB, ws + 4 * m);
 }
 
 template <typename TC>

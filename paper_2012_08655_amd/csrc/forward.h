@@ -60,7 +60,8 @@ struct BatchHeader {
 struct PlanBuffers {
     int32_t* radius;   // [nfrag] radius of each fragment
     int32_t* okey;     // [nfrag] (ring, angle bin) cell of each fragment for the queue order
-    int32_t* order;    // [nslots] queue: work item ids (-1 = empty slot), see the order kernel
+    int32_t* order;    // [nslots][2] queue: (work item id, radius word) per slot (id -1 = empty
+                       // slot), see the order kernel
     void* weights;     // [nfrag][wstride] normalised taps, float (u8/f32) or double (f64)
 };
 

@@ -302,7 +302,6 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
         return;
     }
     const int tid = threadIdx.x;
-    const TC* __restrict__ w = wts + (size_t)gid * a.wstride;
     const Geom g = geom(r, F.bw, F.bh);
     const int SR = min(min(a.strip_rows, kStripMax), g.TH);
     // 8-bit input: the symmetric horizontal pass wants each output's centre on a 4-sample group,
@@ -312,8 +311,22 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
     const int TW = g.TW + sh;
     const int TP = tile_pitch(TW, sizeof(TS));
     const int IP = inter_pitch(g.TH, sizeof(TC));
-    TS* tile = reinterpret_cast<TS*>(smem + kTileLead);
-    TC* inter = reinterpret_cast<TC*>(smem + kTileLead + align16((size_t)SR * TP * sizeof(TS)));  // [column][row]
+    // The fragment's taps are copied to LDS once (read by the passes as broadcast LDS loads, so
+    // the inner loops wait on LDS only): w[0 .. N-1] = w_{-r} .. w_r, then for the symmetric
+    // pass ws[j] = w_{j+1} (j = 0 .. r-1) at a 16-byte boundary.
+    TC* w = reinterpret_cast<TC*>(smem + kTileLead);
+    TC* ws = w + round_up(g.N, 4);
+    TS* tile = reinterpret_cast<TS*>(smem + kTileLead + tap_lds_bytes(a.r_cap, sizeof(TC)));
+    TC* inter = reinterpret_cast<TC*>(reinterpret_cast<unsigned char*>(tile) +
+                                      align16((size_t)SR * TP * sizeof(TS)));  // [column][row]
+    {
+        const TC* __restrict__ wg = wts + (size_t)gid * a.wstride;
+        for (int i = tid; i < g.N; i += kThreads) {
+            const TC v = wg[i];
+            w[i] = v;
+            if (kSym && i > r) ws[i - r - 1] = v;
+        }
+    }
     const TIn* in = static_cast<const TIn*>(d.in);
     TOut* out = static_cast<TOut*>(d.out);
     const int nst = (g.TH + SR - 1) / SR;
@@ -341,7 +354,7 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
             TC acc[kPH];
 #pragma unroll
             for (int p = 0; p < kPH; ++p) acc[p] = 0;
-            if constexpr (kSym) hconv_sym(acc, tile + ty * TP + x0 + r + sh, r, w + r);
+            if constexpr (kSym) hconv_sym(acc, tile + ty * TP + x0 + r + sh, r, w[r], ws);
             else hconv(acc, tile + ty * TP + x0, g.N, w);
             TC* dst = inter + x0 * IP + s0 + ty;
 #pragma unroll
@@ -388,7 +401,8 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
     const int nframes = a.hdr ? a.hdr[0] : a.nframes;
     const int L = a.split_log2;
     for (int q = blockIdx.x; q < nslots; q += gridDim.x) {
-        int item = order[q];
+        const int2 ent = reinterpret_cast<const int2*>(order)[q];  // (work item, radius word)
+        int item = ent.x;
         if (item < 0) {  // empty slot
             if (!PERSIST) break;
             continue;
@@ -400,7 +414,7 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
             item &= kChanItemMask;
         }
         const int gid = item >> (2 * L);
-        const int rr = radius[gid];
+        const int rr = ent.y;
         const int r = rr & 0xFFFF;
         Frag F = describe(table, prefix, nframes, gid);
         if (rr >> 16) {  // merged with the fragment below (same taps): one taller tile
@@ -536,7 +550,8 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
 // order inside one (ring, angle bin) cell is arbitrary and results do not
 // depend on it.
 
-__global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t* __restrict__ okey, int n_arg,
+__global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t* __restrict__ okey,
+                                                                  const int32_t* __restrict__ radius, int n_arg,
                                                                   int L, int nrings, int nang, int nslots_arg,
                                                                   const int32_t* __restrict__ hdr,
                                                                   int32_t* __restrict__ order, int cs_rmax,
@@ -606,19 +621,21 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
         if (lane == 0) total_extra = carry;
     }
     __syncthreads();
+    int2* ord = reinterpret_cast<int2*>(order);
     for (int i = tid; i < n; i += kOrderThreads) {
         const int key = okey[i >> (2 * L)];
         if (key < 0) continue;
+        const int rr = radius[i >> (2 * L)];
         const int ring = key / nang;
         const int j = atomicAdd(&cells[key], 1);  // rank in the ring
         const int m = ring_n[ring];
         const int arc = (j * kXcds) / m;                  // arc a holds ranks [ceil(a m/8), ceil((a+1) m/8))
         const int k = j - (arc * m + kXcds - 1) / kXcds;  // rank inside the arc
         if (ring < small0) {
-            order[ring_base[ring] + kXcds * k + arc] = i;
+            ord[ring_base[ring] + kXcds * k + arc] = make_int2(i, rr);
         } else {  // one slot per channel, consecutive slots of the same XCD
             const int e = total_slots + chan_base[ring] + kXcds * k * cmax + arc;
-            for (int ch = 0; ch < cmax; ++ch) order[e + kXcds * ch] = i | kChanItem | (ch << kChanShift);
+            for (int ch = 0; ch < cmax; ++ch) ord[e + kXcds * ch] = make_int2(i | kChanItem | (ch << kChanShift), rr);
         }
     }
     // empty slots: arc a of a ring of m holds ceil((a+1)m/8) - ceil(a m/8) fragments, ceil(m/8)
@@ -630,13 +647,13 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
         if (sz == per) continue;
         const int k = per - 1;
         if (ring < small0) {
-            order[ring_base[ring] + kXcds * k + arc] = -1;
+            ord[ring_base[ring] + kXcds * k + arc] = make_int2(-1, 0);
         } else {
             const int e = total_slots + chan_base[ring] + kXcds * k * cmax + arc;
-            for (int ch = 0; ch < cmax; ++ch) order[e + kXcds * ch] = -1;
+            for (int ch = 0; ch < cmax; ++ch) ord[e + kXcds * ch] = make_int2(-1, 0);
         }
     }
-    for (int q = total_slots + total_extra + tid; q < nslots; q += kOrderThreads) order[q] = -1;
+    for (int q = total_slots + total_extra + tid; q < nslots; q += kOrderThreads) ord[q] = make_int2(-1, 0);
 }
 
 // Device plan for foveate_plan(): sigma and radius only.
@@ -683,7 +700,8 @@ fov_status launch_typed(const FwdLaunch& a, size_t lds, const PlanBuffers& plan,
                        nrings, nang, wts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "plan kernel launch");
-    hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.okey, a.nfrag,
+    hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.okey,
+                       (const int32_t*)plan.radius, a.nfrag,
                        a.split_log2, nrings, nang, a.nslots, a.hdr, plan.order, a.cs_rmax, a.cmax);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "order kernel launch");
@@ -701,7 +719,7 @@ int queue_slots(int nitems, int r_cap) { return nitems + kXcds * order_rings(r_c
 int queue_slots_by_channel(int nfrag, int r_cap, int cmax) { return cmax * queue_slots(nfrag, r_cap); }
 
 size_t plan_bytes(int nfrag, int nslots, int wstride, int wsize) {
-    return 2 * align16((size_t)nfrag * 4) + align16((size_t)nslots * 4) + 256 + (size_t)nfrag * wstride * wsize;
+    return 2 * align16((size_t)nfrag * 4) + align16((size_t)nslots * 8) + 256 + (size_t)nfrag * wstride * wsize;
 }
 
 PlanBuffers carve_plan(void* ws, int nfrag, int nslots) {
@@ -711,7 +729,7 @@ PlanBuffers carve_plan(void* ws, int nfrag, int nslots) {
     p.radius = reinterpret_cast<int32_t*>(base);
     p.okey = reinterpret_cast<int32_t*>(base + f4);
     p.order = reinterpret_cast<int32_t*>(base + 2 * f4);
-    p.weights = base + 2 * f4 + align16((size_t)nslots * 4) + 256;
+    p.weights = base + 2 * f4 + align16((size_t)nslots * 8) + 256;
     return p;
 }
 
@@ -726,7 +744,8 @@ size_t forward_lds_bytes(int in_dtype, int r_cap, int tile_w, int tile_h, int st
     const int es = stage_size(in_dtype), ec = compute_size(in_dtype);
     // 8-bit input: (-r) mod 4 leading columns; 2r + ((-r) mod 4) never decreases with r, so r_cap sizes them
     const int TW = g.TW + (in_dtype == FOV_U8 ? ((-r_cap) & 3) : 0);
-    return kTileLead + align16((size_t)rows * tile_pitch(TW, es) * es) + (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec + 64;
+    return kTileLead + tap_lds_bytes(r_cap, ec) + align16((size_t)rows * tile_pitch(TW, es) * es) +
+           (size_t)g.G * kPH * inter_pitch(g.TH, ec) * ec + 64;
 }
 
 fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_t lds, const PlanBuffers& plan,
