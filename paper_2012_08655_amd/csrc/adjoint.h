@@ -10,29 +10,32 @@ namespace fov {
 // as for the forward, in a FwdLaunch).
 struct AdjShape {
     int32_t bmax;     // largest fragment side
-    int32_t sw;       // row stride of the horizontal-transpose scratch: bmax + 2 r_cap
+    int32_t sw;       // columns of a transposed window in scratch: bmax + 2 r_cap
+    int32_t sh;       // column stride of a window in scratch: bmax + 2 r_cap rounded up to 4
     int32_t cmax;     // largest channel count
-    int32_t pitch_a;  // LDS row pitch of the horizontal kernel
-    int32_t chunk_c;  // channels the horizontal kernel stages at once
-    int32_t pad_b;    // zero rows above and below a staged fragment in the vertical kernel
-    int32_t pitch_b;  // LDS column pitch of the vertical kernel
-    int32_t tasks_v;  // vertical kernel: output tasks per thread (1, 2 or 4)
-    int32_t chunk_v;  // vertical kernel: channels staged together
+    int32_t pitch_a;  // LDS row pitch of the vertical transpose's rows (zero columns around the data)
+    int32_t pad_b;    // zero rows above a staged gradient column
+    int32_t pitch_b;  // LDS column pitch of the staged gradient
+    int32_t rows_r;   // window rows the window kernel transposes per run (a multiple of 4)
 };
+
+// LDS the window kernel aims to stay within (the window's rows are transposed in runs beyond it).
+constexpr size_t kAdjLdsBudget = (size_t)96 << 10;
 
 // Leading zero taps before each fragment's weights: windows may start up to
 // three taps early (to keep 16-byte LDS loads aligned) and read zeros there.
 constexpr int kAdjWeightLead = 4;
 
 AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax);
-size_t adjoint_lds_h(const AdjShape& s, int es);
-size_t adjoint_lds_v(const AdjShape& s, int es);
+// Dynamic LDS of the window kernel.
+size_t adjoint_lds(const AdjShape& s, int es);
 // Scratch elements for nfrag fragments.
 size_t adjoint_scratch_elems(const AdjShape& s, int nfrag);
 
-// Horizontal-transpose and vertical-gather kernels after the plan kernel has
-// run for `a` (weights at plan.weights + kAdjWeightLead elements, stride
-// a.wstride).  es = 4 (float) or 8 (double).
+// Window and sum kernels after the plan kernel has run for `a` (weights at
+// plan.weights + kAdjWeightLead elements, stride a.wstride): each fragment's
+// transposed window into scratch, then every output tile as the sum of the
+// windows that reach it.  es = 4 (float) or 8 (double).
 fov_status launch_adjoint(const FwdLaunch& a, const AdjShape& s, int es, const PlanBuffers& plan, void* weights_base,
                           void* scratch, hipStream_t stream, size_t lds_limit);
 
