@@ -506,7 +506,7 @@ fov_status run_forward(const std::vector<FrameDesc>& frames, int in_dtype, int o
 // processed in groups whose scratch stays below this (one frame at least).
 constexpr size_t kAdjScratchMax = (size_t)256 << 20;
 
-// Adjoint of one frame group on `stream`: plan, horizontal transpose, vertical gather.
+// Adjoint of one frame group on `stream`: transposed windows, then the per-tile sums.
 fov_status run_backward_group(const FrameDesc* frames, int nf, int dtype, hipStream_t stream) {
     fov_status s;
     const DeviceInfo* dev = nullptr;
@@ -527,27 +527,18 @@ fov_status run_backward_group(const FrameDesc* frames, int nf, int dtype, hipStr
     a.nframes = nf;
     a.nfrag = (int32_t)total;
     a.r_cap = cs.r_cap;
-    a.wstride = round_up(2 * cs.r_cap + 1 + kAdjWeightLead, 16);
     const size_t f4 = ((size_t)a.nfrag * 4 + 255) / 256 * 256;
-    const size_t wbytes = (((size_t)kAdjWeightLead + (size_t)a.nfrag * a.wstride) * es + 255) / 256 * 256;
     const size_t tbytes = frame_table_bytes(nf);
     const size_t sbytes = adjoint_scratch_elems(sh, a.nfrag) * es;
     Workspace* ws = nullptr;
     std::unique_lock<std::mutex> hold;
-    if ((s = workspace(stream, 2 * f4 + wbytes + tbytes + sbytes, nf > kArgFrames ? tbytes : 0, &ws, &hold)) !=
-        FOV_OK)
-        return s;
+    if ((s = workspace(stream, f4 + tbytes + sbytes, nf > kArgFrames ? tbytes : 0, &ws, &hold)) != FOV_OK) return s;
     char* base = static_cast<char*>(ws->dev);
-    PlanBuffers plan;
-    plan.radius = reinterpret_cast<int32_t*>(base);
-    plan.okey = reinterpret_cast<int32_t*>(base + f4);
-    plan.order = nullptr;
-    char* wbase = base + 2 * f4;
-    plan.weights = wbase + (size_t)kAdjWeightLead * es;
-    char* dtab = wbase + wbytes;
+    int32_t* radius = reinterpret_cast<int32_t*>(base);
+    char* dtab = base + f4;
     void* scratch = dtab + tbytes;
     if ((s = stage_frame_table(frames, nf, prefix.data(), ws, dtab, tbytes, stream, &a)) != FOV_OK) return s;
-    return launch_adjoint(a, sh, es, plan, wbase, scratch, stream, dev->lds_limit);
+    return launch_adjoint(a, sh, es, radius, scratch, stream, dev->lds_limit);
 }
 
 fov_status run_backward(const fov_tensor* go, const fov_tensor* gi, const fov_params* p, int32_t np,

@@ -17,13 +17,16 @@ struct AdjShape {
     int32_t pad_b;    // zero rows above a staged gradient column
     int32_t pitch_b;  // LDS column pitch of the staged gradient
     int32_t rows_r;   // window rows the window kernel transposes per run (a multiple of 4)
+    int32_t tap_stride;  // LDS elements per copy of the taps (a multiple of 4)
+    int32_t tap_elems;   // LDS elements of the tap copies (16 / element size copies)
 };
 
 // LDS the window kernel aims to stay within (the window's rows are transposed in runs beyond it).
 constexpr size_t kAdjLdsBudget = (size_t)96 << 10;
 
-// Leading zero taps before each fragment's weights: windows may start up to
-// three taps early (to keep 16-byte LDS loads aligned) and read zeros there.
+// Leading zero taps before each copy of a fragment's taps in LDS: windows may
+// start up to three taps early (to keep 16-byte LDS loads aligned) and read
+// zeros there.
 constexpr int kAdjWeightLead = 4;
 
 AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax);
@@ -32,11 +35,11 @@ size_t adjoint_lds(const AdjShape& s, int es);
 // Scratch elements for nfrag fragments.
 size_t adjoint_scratch_elems(const AdjShape& s, int nfrag);
 
-// Window and sum kernels after the plan kernel has run for `a` (weights at
-// plan.weights + kAdjWeightLead elements, stride a.wstride): each fragment's
-// transposed window into scratch, then every output tile as the sum of the
+// Window and sum kernels for the fragments of `a`: each fragment's radius and
+// taps (written to radius[], one entry per fragment, for the sum kernel) and
+// its transposed window into scratch, then every output tile as the sum of the
 // windows that reach it.  es = 4 (float) or 8 (double).
-fov_status launch_adjoint(const FwdLaunch& a, const AdjShape& s, int es, const PlanBuffers& plan, void* weights_base,
-                          void* scratch, hipStream_t stream, size_t lds_limit);
+fov_status launch_adjoint(const FwdLaunch& a, const AdjShape& s, int es, int32_t* radius, void* scratch,
+                          hipStream_t stream, size_t lds_limit);
 
 }  // namespace fov

@@ -56,35 +56,104 @@ __device__ __forceinline__ Window window_of(const Frag& F, int r, int h, int w) 
     return v;
 }
 
+// Frame buffers as global-memory pointers (pointers read from the frame table would otherwise be
+// accessed with flat instructions).
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(T* p) {
+    return (global_ptr<T>)p;
+}
+
+// Fragment gid of the launch, its frame read from the kernel arguments (ARGS: launches of up to
+// kArgFrames frames) or from the device table.
+template <bool ARGS>
+__device__ __forceinline__ Frag frag_of(const FwdLaunch& a, const FrameDesc* __restrict__ table,
+                                        const int32_t* __restrict__ prefix, int gid) {
+    if constexpr (ARGS) {
+        int f = 0;
+        while (f + 1 < a.nframes && gid >= a.kprefix[f + 1]) ++f;
+        return describe_at(&a.fr[f], a.kprefix[f], gid);
+    } else {
+        return describe(table, prefix, a.nframes, gid);
+    }
+}
+
+// The fragment's taps in LDS: V copies (V = 16 / sizeof(T)), copy k holding tap i at element
+// k * stride + kAdjWeightLead + k + i (stride a multiple of 4) with zeros around, so that a run of
+// taps starting at any tap t >= -kAdjWeightLead + 1 starts on a 16-byte boundary in one of them and
+// is read with 16-byte loads.
+template <typename T>
+__device__ __forceinline__ const T* taps_from(const T* taps, int stride, int t) {
+    constexpr int V = 16 / sizeof(T);
+    const int k = (-t) & (V - 1);
+    return static_cast<const T*>(__builtin_assume_aligned(taps + k * stride + kAdjWeightLead + k + t, 16));
+}
+
 // Transposed window of fragment gid into scratch[gid][c][x - x0][y - y0] (column-major, column
-// stride s.sh) for the frame columns x0..x1 and rows y0..y1-1 of its folded window.  GV: gradient
-// values a thread holds per channel (bh * bw <= 256 GV).
-template <typename T, int GV>
+// stride s.sh) for the frame columns x0..x1 and rows y0..y1-1 of its folded window.  Workgroup
+// q takes fragment q / csplit and its channel share q % csplit (csplit workgroups per fragment).
+// GV: gradient values a thread holds per channel (bh * bw <= 256 GV).
+template <typename T, int GV, bool ARGS>
 __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunch a, const AdjShape s,
                                                                   const FrameDesc* __restrict__ table,
                                                                   const int32_t* __restrict__ prefix,
-                                                                  const int32_t* __restrict__ radius,
-                                                                  const T* __restrict__ wts,
-                                                                  T* __restrict__ scratch) {
+                                                                  int32_t* __restrict__ radius,
+                                                                  T* __restrict__ scratch, int csplit) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = 16 / sizeof(T);  // elements per aligned 16-byte LDS load
     const int PB = s.pitch_b, PAD = s.pad_b, P = s.pitch_a;
-    T* G = reinterpret_cast<T*>(smem);  // [bmax columns][PB rows]: one channel's gradient, rows PAD..
-    T* R = G + (size_t)s.bmax * PB;     // [s.rows_r rows][P]: vertical transpose of a run of window
-                                        // rows, columns kPadA..
-    const int gid = blockIdx.x;
-    const Frag F = describe(table, prefix, a.nframes, gid);
+    T* taps = reinterpret_cast<T*>(smem);  // V shifted copies of the taps (taps_from)
+    T* G = taps + s.tap_elems;             // [bmax columns][PB rows]: one channel's gradient, rows PAD..
+    T* R = G + (size_t)s.bmax * PB;        // [s.rows_r rows][P]: vertical transpose of a run of window
+                                           // rows, columns kPadA..
+    __shared__ double part_of_wave[kThreads / 64];
+    const int gid = blockIdx.x / csplit, share = blockIdx.x - gid * csplit;
+    const Frag F = frag_of<ARGS>(a, table, prefix, gid);
     const FrameDesc& d = *F.fd;
-    const int r = radius[gid];
-    const T* __restrict__ w = wts + (size_t)gid * a.wstride;
+    const int per = (s.cmax + csplit - 1) / csplit;
+    const int c_begin = share * per, c_end = min(d.c, c_begin + per);
+    if (c_begin >= c_end) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    // Radius and normalised taps of the fragment (its sigma from the midpoint's eccentricity, Sec. 2;
+    // Eq. 1 cut at 3 sigma), as the forward's plan computes them.
+    const FrameParams& fp = d.p;
+    const double sigma = fp.sigma_map ? clip_map_sigma((double)as_global(fp.sigma_map)[F.lb], fp.cap)
+                                      : fragment_sigma_ramp(fp, F.bx, F.by);
+    const int r = min(radius_of(sigma), a.r_cap);
+    const int N = 2 * r + 1;
+    if (share == 0 && tid == 0) radius[gid] = r;  // for the sum kernel
+    const double inv = r > 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
+    double part = 0.0;
+    for (int j = tid; j < N; j += kThreads) {
+        const double k = (double)(j - r);
+        part += exp(-(k * k) * inv);
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    if (lane == 0) part_of_wave[wave] = part;
     const Window win = window_of(F, r, d.h, d.w);
     const int RT = win.y1 - win.y0;
     const int CH = s.rows_r;  // window rows transposed per run (a multiple of 4)
-    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-    // Zero padding around the data: written once, never overwritten (every channel and run writes
-    // the same data cells only).
+    // Zero padding around the data and the taps: written once, never overwritten (every channel and
+    // run writes the same data cells only).
+    for (int i = tid; i < s.tap_elems; i += kThreads) {
+        const int k = i / s.tap_stride, j = i - k * s.tap_stride - kAdjWeightLead - k;
+        if (k >= V || j < 0 || j >= N) taps[i] = (T)0;
+    }
     for (int i = tid; i < s.bmax * PB + min(RT, CH) * P; i += kThreads) G[i] = (T)0;
-    const T* g = static_cast<const T*>(d.in);
+    __syncthreads();
+    part = 0.0;
+#pragma unroll
+    for (int q = 0; q < kThreads / 64; ++q) part += part_of_wave[q];
+    for (int j = tid; j < N; j += kThreads) {
+        const double k = (double)(j - r);
+        const T v = (T)(exp(-(k * k) * inv) / part);
+#pragma unroll
+        for (int c = 0; c < V; ++c) taps[c * s.tap_stride + kAdjWeightLead + c + j] = v;
+    }
+    const T* __restrict__ w = taps + kAdjWeightLead;  // copy 0, w[i] = tap i (i = t + r)
+    const global_ptr<const T> g = as_global(static_cast<const T*>(d.in));
     T* dst0 = scratch + (size_t)gid * s.cmax * s.sw * s.sh;
     const int G8 = (win.x1 - win.x0 + kPH) / kPH;
     // One channel's gradient in registers (lanes along a row: coalesced reads); the next channel's
@@ -102,8 +171,8 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
             }
         }
     };
-    load_g(0);
-    for (int c = 0; c < d.c; ++c) {
+    load_g(c_begin);
+    for (int c = c_begin; c < c_end; ++c) {
         __syncthreads();  // zero fill visible; the previous channel's LDS reads are done
         // the fragment's gradient, column-major
 #pragma unroll
@@ -114,7 +183,7 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
                 G[x * PB + PAD + py] = gv[k];
             }
         }
-        if (c + 1 < d.c) load_g(c + 1);
+        if (c + 1 < c_end) load_g(c + 1);
         for (int cr0 = win.y0; cr0 < win.y1; cr0 += CH) {
         const int rows = min(CH, win.y1 - cr0);  // window rows cr0 .. cr0 + rows - 1 in this run
         const int ngroups = (rows + kPV - 1) / kPV;
@@ -136,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
 #pragma unroll
             for (int p = 0; p < kPV; ++p) acc[p] = 0;
             const T* col = G + x * PB + PAD - F.ya;  // col[y]: the gradient at frame row y (zero outside)
-            if (t_lo <= t_hi) vconv(acc, col + y0 + t_lo, t_hi - t_lo + 1, w + (t_lo + r));
+            if (t_lo <= t_hi) vconv(acc, col + y0 + t_lo, t_hi - t_lo + 1, taps_from(taps, s.tap_stride, t_lo + r));
             if (y0 == 0) {  // row 0 collects the taps off the top edge
                 T cdf = 0, corr = 0;
                 for (int m = -r; m <= -F.ya - 1; ++m) {
@@ -183,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
             for (int p = 0; p < kPH; ++p) acc[p] = 0;
             if (t_lo <= t_hi) {
                 t_lo -= (X + t_lo - F.xa + kPadA) & (V - 1);  // aligned window start; taps below -r are zero
-                hconv(acc, rr + X + t_lo, t_hi - t_lo + 1, w + (t_lo + r));
+                hconv(acc, rr + X + t_lo, t_hi - t_lo + 1, taps_from(taps, s.tap_stride, t_lo + r));
             }
             if (win.x0 == 0 && gi == 0) {  // column 0 collects the taps that fell off the left edge
                 T cdf = 0, corr = 0;
@@ -230,30 +299,9 @@ constexpr int sum_batch() {
 }
 
 struct SumNb {
-    int b;  // fragment, -1 = none left
+    int b;  // fragment
     Window w;
 };
-
-// Next fragment after (by, bx) in row-major order whose window meets Q; advances (by, bx).
-__device__ __forceinline__ SumNb next_window(const Frag& Q, int first, int nbx, int bx_lo, int bx_hi, int by_hi,
-                                             const int32_t* __restrict__ radius, int h, int w, int& by, int& bx) {
-    SumNb n;
-    n.b = -1;
-    while (by <= by_hi) {
-        const int b = first + by * nbx + bx;
-        if (++bx > bx_hi) {
-            bx = bx_lo;
-            ++by;
-        }
-        const Frag Fb = describe_at(Q.fd, first, b);
-        const Window wb = window_of(Fb, radius[b], h, w);
-        if (wb.x1 < Q.xa || wb.x0 >= Q.xa + Q.bw || wb.y1 <= Q.ya || wb.y0 >= Q.ya + Q.bh) continue;
-        n.b = b;
-        n.w = wb;
-        break;
-    }
-    return n;
-}
 
 template <typename T, int PIX>
 __device__ __forceinline__ void load_window(T (&v)[kSumCh][PIX], const SumNb& n, const T* __restrict__ scratch,
@@ -271,14 +319,16 @@ __device__ __forceinline__ void load_window(T (&v)[kSumCh][PIX], const SumNb& n,
     }
 }
 
-template <typename T, int PIX>
+__device__ __forceinline__ int lane_value(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+
+template <typename T, int PIX, bool ARGS>
 __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a, const AdjShape s,
                                                                const FrameDesc* __restrict__ table,
                                                                const int32_t* __restrict__ prefix,
                                                                const int32_t* __restrict__ radius,
                                                                const T* __restrict__ scratch) {
     const int gid = blockIdx.x;
-    const Frag Q = describe(table, prefix, a.nframes, gid);
+    const Frag Q = frag_of<ARGS>(a, table, prefix, gid);
     const FrameDesc& d = *Q.fd;
     const FrameParams& fp = d.p;
     const int nbx = fp.nbx, nby = d.nby;
@@ -286,6 +336,8 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
     const int K = (a.r_cap + fp.block - 1) / fp.block;  // fragments within reach on each side
     const int by_lo = max(Q.by - K, 0), by_hi = min(Q.by + K, nby - 1);
     const int bx_lo = max(Q.bx - K, 0), bx_hi = min(Q.bx + K, nbx - 1);
+    const int nx = bx_hi - bx_lo + 1, ncand = nx * (by_hi - by_lo + 1);
+    const int lane = threadIdx.x & 63;
     const int npix = Q.bw * Q.bh;
     int px[PIX], py[PIX];  // frame column and row of each pixel (-1: none)
 #pragma unroll
@@ -294,7 +346,8 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
         px[k] = i < npix ? Q.xa + i / Q.bh : -1;
         py[k] = i < npix ? Q.ya + i % Q.bh : -1;
     }
-    T* out = static_cast<T*>(d.out);
+    const global_ptr<T> out = as_global(static_cast<T*>(d.out));
+    constexpr int kSumBatch = sum_batch<T, PIX>();
     for (int c0 = 0; c0 < d.c; c0 += kSumCh) {
         const int cc = min(kSumCh, d.c - c0);
         T acc[kSumCh][PIX];
@@ -302,33 +355,50 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
         for (int ch = 0; ch < kSumCh; ++ch)
 #pragma unroll
             for (int k = 0; k < PIX; ++k) acc[ch][k] = 0;
-        int by = by_lo, bx = bx_lo;
-        for (;;) {
-            // the next kSumBatch windows that reach the tile: their loads all in flight, then added
-            // in order
-            constexpr int kSumBatch = sum_batch<T, PIX>();
-            SumNb nb[kSumBatch];
-            int cnt = 0;
-#pragma unroll
-            for (int j = 0; j < kSumBatch; ++j) {
-                nb[j] = next_window(Q, first, nbx, bx_lo, bx_hi, by_hi, radius, d.h, d.w, by, bx);
-                cnt += nb[j].b >= 0 ? 1 : 0;
-                if (nb[j].b < 0) break;
+        for (int j0 = 0; j0 < ncand; j0 += 64) {
+            // Candidates j0 .. j0 + 63 (row-major over the fragments within reach), one per lane: the
+            // ballot of those whose window meets the tile lists them in the fixed summation order.
+            const int j = j0 + lane;
+            int b = 0, y0 = 0, y1 = 0, x0 = 0, x1 = 0;
+            bool hit = false;
+            if (j < ncand) {
+                const int jy = j / nx;
+                b = first + (by_lo + jy) * nbx + bx_lo + (j - jy * nx);
+                const Window wb = window_of(describe_at(Q.fd, first, b), radius[b], d.h, d.w);
+                hit = wb.x1 >= Q.xa && wb.x0 < Q.xa + Q.bw && wb.y1 > Q.ya && wb.y0 < Q.ya + Q.bh;
+                y0 = wb.y0, y1 = wb.y1, x0 = wb.x0, x1 = wb.x1;
             }
-            if (cnt == 0) break;
-            T v[kSumBatch][kSumCh][PIX];
+            uint64_t m = __ballot(hit);
+            while (m) {
+                // the next kSumBatch of them: all their loads in flight, then added in order
+                SumNb nb[kSumBatch];
+                int cnt = 0;
 #pragma unroll
-            for (int j = 0; j < kSumBatch; ++j)
-                if (j < cnt) load_window(v[j], nb[j], scratch, s, c0, cc, px, py);
-#pragma unroll
-            for (int j = 0; j < kSumBatch; ++j)
-                if (j < cnt) {
-#pragma unroll
-                    for (int ch = 0; ch < kSumCh; ++ch)
-#pragma unroll
-                        for (int k = 0; k < PIX; ++k) acc[ch][k] += v[j][ch][k];
+                for (int q = 0; q < kSumBatch; ++q) {
+                    if (m) {
+                        const int l = __builtin_ctzll(m);
+                        m &= m - 1;
+                        nb[q].b = lane_value(b, l);
+                        nb[q].w.y0 = lane_value(y0, l);
+                        nb[q].w.y1 = lane_value(y1, l);
+                        nb[q].w.x0 = lane_value(x0, l);
+                        nb[q].w.x1 = lane_value(x1, l);
+                        ++cnt;
+                    }
                 }
-            if (cnt < kSumBatch) break;
+                T v[kSumBatch][kSumCh][PIX];
+#pragma unroll
+                for (int q = 0; q < kSumBatch; ++q)
+                    if (q < cnt) load_window(v[q], nb[q], scratch, s, c0, cc, px, py);
+#pragma unroll
+                for (int q = 0; q < kSumBatch; ++q)
+                    if (q < cnt) {
+#pragma unroll
+                        for (int ch = 0; ch < kSumCh; ++ch)
+#pragma unroll
+                            for (int k = 0; k < PIX; ++k) acc[ch][k] += v[q][ch][k];
+                    }
+            }
         }
 #pragma unroll
         for (int k = 0; k < PIX; ++k) {
@@ -340,30 +410,39 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
     }
 }
 
-template <typename T>
-fov_status launch_typed(const FwdLaunch& a, const AdjShape& s, const PlanBuffers& plan, void* scratch,
-                        hipStream_t stream, size_t lds_limit) {
-    const bool small = s.bmax * s.bmax <= 4 * kThreads;  // fragments of at most 32 x 32 pixels
-    auto kw = small ? fov_adj_window_kernel<T, 4> : fov_adj_window_kernel<T, kMaxBlock * kMaxBlock / kThreads>;
+// One window workgroup per fragment and channel (else per fragment).
+constexpr bool kWindowSplit = true;
+
+template <typename T, int GV, bool ARGS>
+fov_status launch_kernels(const FwdLaunch& a, const AdjShape& s, int32_t* radius, T* sc, hipStream_t stream,
+                          size_t lds_limit) {
+    const auto kw = fov_adj_window_kernel<T, GV, ARGS>;
     fov_status st;
     if ((st = allow_dyn_lds((const void*)kw, lds_limit)) != FOV_OK) return st;
-    const T* wts = static_cast<const T*>(plan.weights);
-    T* sc = static_cast<T*>(scratch);
-    hipLaunchKernelGGL(kw, dim3(a.nfrag), dim3(kThreads), adjoint_lds(s, sizeof(T)), stream, a, s,
-                       (const FrameDesc*)a.table, (const int32_t*)a.prefix, (const int32_t*)plan.radius, wts, sc);
+    const int csplit = kWindowSplit && (int64_t)a.nfrag * s.cmax * kThreads < ((int64_t)1 << 32) ? s.cmax : 1;
+    hipLaunchKernelGGL(kw, dim3(a.nfrag * csplit), dim3(kThreads), adjoint_lds(s, sizeof(T)), stream, a, s,
+                       (const FrameDesc*)a.table, (const int32_t*)a.prefix, radius, sc, csplit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "adjoint window kernel launch");
-    if (small)
-        hipLaunchKernelGGL((fov_adj_sum_kernel<T, 4>), dim3(a.nfrag), dim3(kThreads), 0, stream, a, s,
-                           (const FrameDesc*)a.table, (const int32_t*)a.prefix, (const int32_t*)plan.radius,
-                           (const T*)sc);
-    else
-        hipLaunchKernelGGL((fov_adj_sum_kernel<T, kMaxBlock * kMaxBlock / kThreads>), dim3(a.nfrag), dim3(kThreads),
-                           0, stream, a, s, (const FrameDesc*)a.table, (const int32_t*)a.prefix,
-                           (const int32_t*)plan.radius, (const T*)sc);
+    hipLaunchKernelGGL((fov_adj_sum_kernel<T, GV, ARGS>), dim3(a.nfrag), dim3(kThreads), 0, stream, a, s,
+                       (const FrameDesc*)a.table, (const int32_t*)a.prefix, (const int32_t*)radius, (const T*)sc);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "adjoint sum kernel launch");
     return FOV_OK;
+}
+
+template <typename T>
+fov_status launch_typed(const FwdLaunch& a, const AdjShape& s, int32_t* radius, void* scratch, hipStream_t stream,
+                        size_t lds_limit) {
+    // values per thread: 4 for fragments of at most 32 x 32 pixels, else kMaxBlock^2 / kThreads
+    constexpr int kBig = kMaxBlock * kMaxBlock / kThreads;
+    const bool small = s.bmax * s.bmax <= 4 * kThreads;
+    T* sc = static_cast<T*>(scratch);
+    if (a.from_args)
+        return small ? launch_kernels<T, 4, true>(a, s, radius, sc, stream, lds_limit)
+                     : launch_kernels<T, kBig, true>(a, s, radius, sc, stream, lds_limit);
+    return small ? launch_kernels<T, 4, false>(a, s, radius, sc, stream, lds_limit)
+                 : launch_kernels<T, kBig, false>(a, s, radius, sc, stream, lds_limit);
 }
 
 }  // namespace
@@ -379,29 +458,28 @@ AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax) {
     const int span = std::min(kPV * (63 / bmax + 1) + kPV - 1, bmax + 2 * r_cap - 1);
     s.pad_b = round_up(span + 4, 4);
     s.pitch_b = inter_pitch(bmax + 2 * s.pad_b, es);
+    s.tap_stride = round_up(2 * r_cap + 1 + kAdjWeightLead + 8, 4);
+    s.tap_elems = (16 / es) * s.tap_stride;
     // window rows transposed per run: the whole window when the LDS stays within kAdjLdsBudget,
     // else as many rows (a multiple of 4, at least 4) as fit beside the staged gradient
-    const size_t g = (size_t)bmax * s.pitch_b * es, row = (size_t)s.pitch_a * es;
+    const size_t g = ((size_t)s.tap_elems + (size_t)bmax * s.pitch_b) * es, row = (size_t)s.pitch_a * es;
     const int fit = g + 4 * row <= kAdjLdsBudget ? (int)((kAdjLdsBudget - g) / row) / 4 * 4 : 4;
     s.rows_r = std::min(round_up(s.sw, 4), fit);
     return s;
 }
 
 size_t adjoint_lds(const AdjShape& s, int es) {
-    return ((size_t)s.bmax * s.pitch_b + (size_t)s.rows_r * s.pitch_a) * es;
+    return ((size_t)s.tap_elems + (size_t)s.bmax * s.pitch_b + (size_t)s.rows_r * s.pitch_a) * es;
 }
 
 size_t adjoint_scratch_elems(const AdjShape& s, int nfrag) { return (size_t)nfrag * s.cmax * s.sw * s.sh; }
 
-fov_status launch_adjoint(const FwdLaunch& a, const AdjShape& s, int es, const PlanBuffers& plan, void* weights_base,
-                          void* scratch, hipStream_t stream, size_t lds_limit) {
+fov_status launch_adjoint(const FwdLaunch& a, const AdjShape& s, int es, int32_t* radius, void* scratch,
+                          hipStream_t stream, size_t lds_limit) {
     if (a.nfrag <= 0) return FOV_OK;
     if (adjoint_lds(s, es) + 64 > lds_limit) return set_error(FOV_ERANGE, "adjoint tiles do not fit in LDS");
-    (void)weights_base;
-    fov_status st = launch_plan_weights(a, es, plan, stream, kAdjWeightLead);
-    if (st != FOV_OK) return st;
-    return es == 8 ? launch_typed<double>(a, s, plan, scratch, stream, lds_limit)
-                   : launch_typed<float>(a, s, plan, scratch, stream, lds_limit);
+    return es == 8 ? launch_typed<double>(a, s, radius, scratch, stream, lds_limit)
+                   : launch_typed<float>(a, s, radius, scratch, stream, lds_limit);
 }
 
 }  // namespace fov

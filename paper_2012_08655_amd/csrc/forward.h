@@ -91,13 +91,6 @@ fov_status launch_forward(const FwdLaunch& a, int in_dtype, int out_dtype, size_
 // in a captured graph); NULL for an unsupported pair.
 const void* forward_main_kernel(int in_dtype, int out_dtype, bool persist);
 
-// Plan kernel alone (radius, order key and normalised taps of every fragment,
-// float taps for wsize 4, double for 8); publishes the frame table when the
-// frames travel in the arguments.  `lead` zero taps are written just before
-// the first fragment's taps.
-fov_status launch_plan_weights(const FwdLaunch& a, int wsize, const PlanBuffers& plan, hipStream_t stream,
-                               int lead = 0);
-
 // Device plan for foveate_plan(): sigma and radius of every fragment.
 fov_status launch_plan(const FrameParams& fp, int nblk, double* sigma_out, int32_t* r_out, hipStream_t stream);
 

@@ -457,9 +457,8 @@ __device__ __forceinline__ int angle_bin(const Frag& F, int nang) {
 template <typename TC>
 __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a, int32_t* __restrict__ radius,
                                                               int32_t* __restrict__ okey, int nrings, int nang,
-                                                              TC* __restrict__ wts, int lead) {
+                                                              TC* __restrict__ wts) {
     const int lane = threadIdx.x;
-    if (blockIdx.x == 0 && lane < lead) wts[lane - lead] = (TC)0;  // zero taps before the first fragment's
     const int nframes = a.hdr ? a.hdr[0] : a.nframes;
     const int nfrag = a.hdr ? a.hdr[1] : a.nfrag;
     for (int gid = blockIdx.x; gid < nfrag; gid += gridDim.x) {
@@ -698,7 +697,7 @@ fov_status launch_typed(const FwdLaunch& a, size_t lds, const PlanBuffers& plan,
     const int nrings = order_rings(a.r_cap), nang = order_angle_bins(nrings);
     const int plan_grid = a.hdr ? std::min(a.nfrag, 8192) : a.nfrag;
     hipLaunchKernelGGL(fov_plan_weights_kernel<TC>, dim3(plan_grid), dim3(64), 0, stream, a, plan.radius, plan.okey,
-                       nrings, nang, wts, 0);
+                       nrings, nang, wts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "plan kernel launch");
     hipLaunchKernelGGL(fov_order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, (const int32_t*)plan.okey,
@@ -783,20 +782,6 @@ const void* forward_main_kernel(int in_dtype, int out_dtype, bool persist) {
         return persist ? (const void*)fov_fwd_kernel<double, double, double, double, true>
                        : (const void*)fov_fwd_kernel<double, double, double, double, false>;
     return nullptr;
-}
-
-fov_status launch_plan_weights(const FwdLaunch& a, int wsize, const PlanBuffers& plan, hipStream_t stream, int lead) {
-    if (a.nfrag <= 0) return FOV_OK;
-    const int nrings = order_rings(a.r_cap), nang = order_angle_bins(nrings);
-    if (wsize == 8)
-        hipLaunchKernelGGL(fov_plan_weights_kernel<double>, dim3(a.nfrag), dim3(64), 0, stream, a, plan.radius,
-                           plan.okey, nrings, nang, static_cast<double*>(plan.weights), lead);
-    else
-        hipLaunchKernelGGL(fov_plan_weights_kernel<float>, dim3(a.nfrag), dim3(64), 0, stream, a, plan.radius,
-                           plan.okey, nrings, nang, static_cast<float*>(plan.weights), lead);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_error(e, "plan kernel launch");
-    return FOV_OK;
 }
 
 fov_status launch_plan(const FrameParams& fp, int nblk, double* sigma_out, int32_t* r_out, hipStream_t stream) {
