@@ -19,6 +19,7 @@ struct AdjShape {
     int32_t rows_r;   // window rows the window kernel transposes per run (a multiple of 4)
     int32_t tap_stride;  // LDS elements per copy of the taps (a multiple of 4)
     int32_t tap_elems;   // LDS elements of the tap copies (16 / element size copies)
+    uint32_t bdiv;       // ceil(2^32 / bmax) (0 for bmax = 1): i / bmax = mulhi(i, bdiv) for i * bmax < 2^32
 };
 
 // LDS the window kernel aims to stay within (the window's rows are transposed in runs beyond it).
@@ -35,10 +36,10 @@ size_t adjoint_lds(const AdjShape& s, int es);
 // Scratch elements for nfrag fragments.
 size_t adjoint_scratch_elems(const AdjShape& s, int nfrag);
 
-// Window and sum kernels for the fragments of `a`: each fragment's radius and
-// taps (written to radius[], one entry per fragment, for the sum kernel) and
-// its transposed window into scratch, then every output tile as the sum of the
-// windows that reach it.  es = 4 (float) or 8 (double).
+// Window and sum kernels for the fragments of `a`: each fragment's radius
+// (into radius[], one entry per fragment), taps and transposed window into
+// scratch, then every output tile as the sum of the windows that reach it.
+// es = 4 (float) or 8 (double).
 fov_status launch_adjoint(const FwdLaunch& a, const AdjShape& s, int es, int32_t* radius, void* scratch,
                           hipStream_t stream, size_t lds_limit);
 

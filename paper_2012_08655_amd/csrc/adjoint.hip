@@ -56,6 +56,12 @@ __device__ __forceinline__ Window window_of(const Frag& F, int r, int h, int w) 
     return v;
 }
 
+// Sum kernel: neighbours' radii read from radius[] (written by the window kernel), else recomputed.
+constexpr bool kSumLoadsRadius = true;
+
+// x / d for a launch constant d (0 <= x, x * d < 2^32): m = ceil(2^32 / d), 0 for d = 1.
+__device__ __forceinline__ int div_by(int x, uint32_t m) { return m ? (int)__umulhi((uint32_t)x, m) : x; }
+
 // Frame buffers as global-memory pointers (pointers read from the frame table would otherwise be
 // accessed with flat instructions).
 template <typename T>
@@ -64,6 +70,12 @@ using global_ptr = __attribute__((address_space(1))) T*;
 template <typename T>
 __device__ __forceinline__ global_ptr<T> as_global(T* p) {
     return (global_ptr<T>)p;
+}
+
+// Blur strength of fragment (bx, by), local index lb, of a frame: from the sigma map or from the
+// midpoint's eccentricity (Sec. 2).
+__device__ __forceinline__ double fragment_sigma(const FrameParams& fp, int lb, int bx, int by) {
+    return fp.sigma_map ? clip_map_sigma((double)as_global(fp.sigma_map)[lb], fp.cap) : fragment_sigma_ramp(fp, bx, by);
 }
 
 // Fragment gid of the launch, its frame read from the kernel arguments (ARGS: launches of up to
@@ -99,8 +111,8 @@ template <typename T, int GV, bool ARGS>
 __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunch a, const AdjShape s,
                                                                   const FrameDesc* __restrict__ table,
                                                                   const int32_t* __restrict__ prefix,
-                                                                  int32_t* __restrict__ radius,
-                                                                  T* __restrict__ scratch, int csplit) {
+                                                                  int32_t* __restrict__ radius, T* __restrict__ scratch,
+                                                                  int csplit) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = 16 / sizeof(T);  // elements per aligned 16-byte LDS load
     const int PB = s.pitch_b, PAD = s.pad_b, P = s.pitch_a;
@@ -116,89 +128,98 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
     const int c_begin = share * per, c_end = min(d.c, c_begin + per);
     if (c_begin >= c_end) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    const global_ptr<const T> g = as_global(static_cast<const T*>(d.in));
+    // One channel's gradient in registers, thread values i = tid + 256 k at row i / bmax, column
+    // i % bmax (lanes along a row: coalesced reads); the next channel's loads are issued while this
+    // channel is transposed.
+    constexpr int kGv = GV;
+    T gv[kGv];
+    int gy[kGv], gx[kGv];  // row and column of each value (-1: none)
+#pragma unroll
+    for (int k = 0; k < kGv; ++k) {
+        const int i = tid + k * kThreads;
+        const int py = div_by(i, s.bdiv), x = i - py * s.bmax;
+        const bool in = x < F.bw && py < F.bh;
+        gy[k] = in ? py : -1;
+        gx[k] = x;
+    }
+    auto load_g = [&](int c) {
+#pragma unroll
+        for (int k = 0; k < kGv; ++k)
+            if (gy[k] >= 0)
+                gv[k] = g[(int64_t)c * d.isc + (int64_t)(F.ya + gy[k]) * d.ish + (int64_t)(F.xa + gx[k]) * d.isw];
+    };
+    load_g(c_begin);
     // Radius and normalised taps of the fragment (its sigma from the midpoint's eccentricity, Sec. 2;
     // Eq. 1 cut at 3 sigma), as the forward's plan computes them.
     const FrameParams& fp = d.p;
-    const double sigma = fp.sigma_map ? clip_map_sigma((double)as_global(fp.sigma_map)[F.lb], fp.cap)
-                                      : fragment_sigma_ramp(fp, F.bx, F.by);
+    const double sigma = fragment_sigma(fp, F.lb, F.bx, F.by);
     const int r = min(radius_of(sigma), a.r_cap);
     const int N = 2 * r + 1;
-    if (share == 0 && tid == 0) radius[gid] = r;  // for the sum kernel
+    if (kSumLoadsRadius && share == 0 && tid == 0) radius[gid] = r;
     const double inv = r > 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
-    double part = 0.0;
+    double part = 0.0, mine = 0.0;
     for (int j = tid; j < N; j += kThreads) {
         const double k = (double)(j - r);
-        part += exp(-(k * k) * inv);
+        const double e = exp(-(k * k) * inv);
+        part += e;
+        if (j == tid) mine = e;
     }
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
     if (lane == 0) part_of_wave[wave] = part;
     const Window win = window_of(F, r, d.h, d.w);
     const int RT = win.y1 - win.y0;
     const int CH = s.rows_r;  // window rows transposed per run (a multiple of 4)
-    // Zero padding around the data and the taps: written once, never overwritten (every channel and
-    // run writes the same data cells only).
-    for (int i = tid; i < s.tap_elems; i += kThreads) {
-        const int k = i / s.tap_stride, j = i - k * s.tap_stride - kAdjWeightLead - k;
-        if (k >= V || j < 0 || j >= N) taps[i] = (T)0;
+    // Zeros: the taps' padding, and the staged gradient and transposed rows (whose data cells every
+    // channel and run overwrite).
+    for (int k = 0; k < V; ++k)
+        for (int j = tid; j < s.tap_stride; j += kThreads) {
+            const int t = j - kAdjWeightLead - k;
+            if (t < 0 || t >= N) taps[k * s.tap_stride + j] = (T)0;
+        }
+    {
+        using V16 = __attribute__((ext_vector_type(4))) uint32_t;
+        V16* z = reinterpret_cast<V16*>(G);
+        const int n16 = (s.bmax * PB + min(RT, CH) * P) / V;
+        for (int i = tid; i < n16; i += kThreads) z[i] = V16{0, 0, 0, 0};
     }
-    for (int i = tid; i < s.bmax * PB + min(RT, CH) * P; i += kThreads) G[i] = (T)0;
     __syncthreads();
     part = 0.0;
 #pragma unroll
     for (int q = 0; q < kThreads / 64; ++q) part += part_of_wave[q];
     for (int j = tid; j < N; j += kThreads) {
         const double k = (double)(j - r);
-        const T v = (T)(exp(-(k * k) * inv) / part);
+        const T v = (T)((j == tid ? mine : exp(-(k * k) * inv)) / part);
 #pragma unroll
         for (int c = 0; c < V; ++c) taps[c * s.tap_stride + kAdjWeightLead + c + j] = v;
     }
     const T* __restrict__ w = taps + kAdjWeightLead;  // copy 0, w[i] = tap i (i = t + r)
-    const global_ptr<const T> g = as_global(static_cast<const T*>(d.in));
     T* dst0 = scratch + (size_t)gid * s.cmax * s.sw * s.sh;
     const int G8 = (win.x1 - win.x0 + kPH) / kPH;
-    // One channel's gradient in registers (lanes along a row: coalesced reads); the next channel's
-    // loads are issued while this channel is transposed.
-    constexpr int kGv = GV;
-    const int npix = F.bh * F.bw;
-    T gv[kGv];
-    auto load_g = [&](int c) {
-#pragma unroll
-        for (int k = 0; k < kGv; ++k) {
-            const int i = tid + k * kThreads;
-            if (i < npix) {
-                const int py = i / F.bw, x = i - py * F.bw;
-                gv[k] = g[(int64_t)c * d.isc + (int64_t)(F.ya + py) * d.ish + (int64_t)(F.xa + x) * d.isw];
-            }
-        }
-    };
-    load_g(c_begin);
+    // Barriers: one before each run's vertical transpose (the staged gradient and the taps are
+    // visible; the previous run's rows are no longer read) and one after it (the rows are written;
+    // the gradient is no longer read, so the next channel may be staged).
     for (int c = c_begin; c < c_end; ++c) {
-        __syncthreads();  // zero fill visible; the previous channel's LDS reads are done
         // the fragment's gradient, column-major
 #pragma unroll
-        for (int k = 0; k < kGv; ++k) {
-            const int i = tid + k * kThreads;
-            if (i < npix) {
-                const int py = i / F.bw, x = i - py * F.bw;
-                G[x * PB + PAD + py] = gv[k];
-            }
-        }
+        for (int k = 0; k < kGv; ++k)
+            if (gy[k] >= 0) G[gx[k] * PB + PAD + gy[k]] = gv[k];
         if (c + 1 < c_end) load_g(c + 1);
         for (int cr0 = win.y0; cr0 < win.y1; cr0 += CH) {
         const int rows = min(CH, win.y1 - cr0);  // window rows cr0 .. cr0 + rows - 1 in this run
         const int ngroups = (rows + kPV - 1) / kPV;
         const int ntask_v = s.bmax * ngroups;  // task i: column i % bmax, rows cr0 + 4 (i / bmax) .. +3
-        __syncthreads();  // the gradient is staged; the previous run's rows are no longer read
+        __syncthreads();
         // Vertical transpose Fold_y V^T g into R: a wave's 64 tasks share one band of taps (the taps
         // that meet the fragment's rows from some row of the wave).
         for (int i0 = wave * 64; i0 < ntask_v; i0 += kThreads) {
-            const int gA = i0 / s.bmax, gB = min((i0 + 63) / s.bmax, ngroups - 1);
+            const int gA = div_by(i0, s.bdiv), gB = min(div_by(i0 + 63, s.bdiv), ngroups - 1);
             const int ymin = cr0 + kPV * gA, ymax = min(cr0 + kPV * gB + kPV - 1, cr0 + rows - 1);
             int t_lo = max(-r, F.ya - ymax);
             const int t_hi = min(r, F.ya + F.bh - 1 - ymin);
             if (t_lo <= t_hi) t_lo -= (cr0 + kPV * gA + t_lo - F.ya + PAD) & (V - 1);  // aligned start
             const int i = i0 + lane;
-            const int x = i % s.bmax, gr = i / s.bmax;
+            const int gr = div_by(i, s.bdiv), x = i - gr * s.bmax;
             if (x >= F.bw || gr >= ngroups) continue;
             const int y0 = cr0 + kPV * gr;
             T acc[kPV];
@@ -237,9 +258,8 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
         // shares one group of 8 output columns, so the taps that meet the fragment form one
         // wave-uniform range.
         T* dstc = dst0 + (size_t)c * s.sw * s.sh + (cr0 - win.y0);
-        const int nchunk = (rows + 63) / 64;
-        for (int task = wave; task < nchunk * G8; task += kThreads / 64) {
-            const int gi = task / nchunk, ch = task - gi * nchunk;
+        for (int ch = 0; ch * 64 < rows; ++ch)
+        for (int gi = wave; gi < G8; gi += kThreads / 64) {
             const int X = win.x0 + gi * kPH;
             // taps t with X + p + t inside the fragment for some p in 0..7
             int t_lo = max(-r, F.xa - X - (kPH - 1));
@@ -281,7 +301,6 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
                 if (X + p <= win.x1) dst[(size_t)p * s.sh] = acc[p];
         }
         }
-        __syncthreads();  // the next channel restages the gradient
     }
 }
 
@@ -303,18 +322,45 @@ struct SumNb {
     Window w;
 };
 
+// Raw buffer descriptor (dword 3 as gfx9 expects for untyped access).
+constexpr int kBufferWord3 = 0x00020000;
+// Byte offset past any window plane: a buffer load there returns 0.
+constexpr uint32_t kOutside = 0x7fffffffu;
+
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t rsrc, uint32_t voff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc, (int)voff, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)voff, 0, 0));
+}
+
+// The values of window n at this thread's pixels, channels c0 .. c0 + kSumCh - 1 (zero outside the
+// window and for channels >= c0 + cc): one buffer descriptor per channel plane of the window, so a
+// pixel outside it reads 0 through the descriptor's range check.
 template <typename T, int PIX>
 __device__ __forceinline__ void load_window(T (&v)[kSumCh][PIX], const SumNb& n, const T* __restrict__ scratch,
                                             const AdjShape& s, int c0, int cc, const int (&px)[PIX],
                                             const int (&py)[PIX]) {
+    const uint32_t wx = (uint32_t)(n.w.x1 - n.w.x0), wy = (uint32_t)(n.w.y1 - n.w.y0);
+    uint32_t voff[PIX];
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
-        const bool in = px[k] >= n.w.x0 && px[k] <= n.w.x1 && py[k] >= n.w.y0 && py[k] < n.w.y1;
-        const size_t off = (size_t)(px[k] - n.w.x0) * s.sh + (py[k] - n.w.y0);
+        const uint32_t dx = (uint32_t)(px[k] - n.w.x0), dy = (uint32_t)(py[k] - n.w.y0);
+        voff[k] = (dx <= wx && dy < wy) ? (dx * (uint32_t)s.sh + dy) * (uint32_t)sizeof(T) : kOutside;
+    }
+    const int plane = s.sw * s.sh;
 #pragma unroll
-        for (int ch = 0; ch < kSumCh; ++ch) {
-            const T* src = scratch + ((size_t)n.b * s.cmax + c0 + ch) * s.sw * s.sh;
-            v[ch][k] = (in && ch < cc) ? src[off] : (T)0;
+    for (int ch = 0; ch < kSumCh; ++ch) {
+        if (ch < cc) {
+            const T* src = scratch + ((size_t)n.b * s.cmax + c0 + ch) * plane;
+            const __amdgpu_buffer_rsrc_t rsrc =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(src), 0, plane * (int)sizeof(T), kBufferWord3);
+#pragma unroll
+            for (int k = 0; k < PIX; ++k) v[ch][k] = buffer_load<T>(rsrc, voff[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < PIX; ++k) v[ch][k] = (T)0;
         }
     }
 }
@@ -337,16 +383,22 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
     const int by_lo = max(Q.by - K, 0), by_hi = min(Q.by + K, nby - 1);
     const int bx_lo = max(Q.bx - K, 0), bx_hi = min(Q.bx + K, nbx - 1);
     const int nx = bx_hi - bx_lo + 1, ncand = nx * (by_hi - by_lo + 1);
+    const float rnx = 1.0f / (float)nx;  // candidate j is row j / nx of the neighbourhood
     const int lane = threadIdx.x & 63;
-    const int npix = Q.bw * Q.bh;
+    const int B = fp.block;
     int px[PIX], py[PIX];  // frame column and row of each pixel (-1: none)
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
         const int i = threadIdx.x + k * kThreads;
-        px[k] = i < npix ? Q.xa + i / Q.bh : -1;
-        py[k] = i < npix ? Q.ya + i % Q.bh : -1;
+        const int col = div_by(i, s.bdiv), row = i - col * s.bmax;
+        const bool in = col < Q.bw && row < Q.bh;
+        px[k] = in ? Q.xa + col : -1;
+        py[k] = in ? Q.ya + row : -1;
     }
     const global_ptr<T> out = as_global(static_cast<T*>(d.out));
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* tile = reinterpret_cast<T*>(smem);
+    const int LP = s.bmax + 1;
     constexpr int kSumBatch = sum_batch<T, PIX>();
     for (int c0 = 0; c0 < d.c; c0 += kSumCh) {
         const int cc = min(kSumCh, d.c - c0);
@@ -362,11 +414,18 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
             int b = 0, y0 = 0, y1 = 0, x0 = 0, x1 = 0;
             bool hit = false;
             if (j < ncand) {
-                const int jy = j / nx;
-                b = first + (by_lo + jy) * nbx + bx_lo + (j - jy * nx);
-                const Window wb = window_of(describe_at(Q.fd, first, b), radius[b], d.h, d.w);
-                hit = wb.x1 >= Q.xa && wb.x0 < Q.xa + Q.bw && wb.y1 > Q.ya && wb.y0 < Q.ya + Q.bh;
-                y0 = wb.y0, y1 = wb.y1, x0 = wb.x0, x1 = wb.x1;
+                const int jy = (int)(((float)j + 0.5f) * rnx);
+                const int by = by_lo + jy, bx = bx_lo + (j - jy * nx);
+                const int lb = by * nbx + bx;
+                b = first + lb;
+                const int rb = kSumLoadsRadius ? radius[b] : min(radius_of(fragment_sigma(fp, lb, bx, by)), a.r_cap);
+                // its folded window (as window_of gives it for that fragment)
+                const int X0 = fp.origin_x + bx * B, Y0 = fp.origin_y + by * B;
+                x0 = max(X0 - rb, 0);
+                x1 = min(X0 + B - 1 + rb, d.w - 1);
+                y0 = max(Y0 - rb, 0);
+                y1 = min(Y0 + B + rb, d.h);
+                hit = x1 >= Q.xa && x0 < Q.xa + Q.bw && y1 > Q.ya && y0 < Q.ya + Q.bh;
             }
             uint64_t m = __ballot(hit);
             while (m) {
@@ -400,12 +459,26 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
                     }
             }
         }
+        // Through LDS (tile[ch][row][col], pitch bmax + 1) so that the stores run along rows.
+        if (c0 > 0) __syncthreads();  // the previous channels' tile is read
+#pragma unroll
+        for (int ch = 0; ch < kSumCh; ++ch)
+#pragma unroll
+            for (int k = 0; k < PIX; ++k)
+                if (ch < cc && px[k] >= 0) tile[(ch * s.bmax + py[k] - Q.ya) * LP + px[k] - Q.xa] = acc[ch][k];
+        __syncthreads();
+        int tx = threadIdx.x;
+        asm volatile("" : "+v"(tx));  // store addresses computed here, not held through the sums
 #pragma unroll
         for (int k = 0; k < PIX; ++k) {
-            if (px[k] < 0) continue;
+            const int i = tx + k * kThreads;
+            const int row = div_by(i, s.bdiv), col = i - row * s.bmax;
+            if (row >= Q.bh || col >= Q.bw) continue;
 #pragma unroll
             for (int ch = 0; ch < kSumCh; ++ch)
-                if (ch < cc) out[(int64_t)(c0 + ch) * d.osc + (int64_t)py[k] * d.osh + (int64_t)px[k] * d.osw] = acc[ch][k];
+                if (ch < cc)
+                    out[(int64_t)(c0 + ch) * d.osc + (int64_t)(Q.ya + row) * d.osh + (int64_t)(Q.xa + col) * d.osw] =
+                        tile[(ch * s.bmax + row) * LP + col];
         }
     }
 }
@@ -424,7 +497,11 @@ fov_status launch_kernels(const FwdLaunch& a, const AdjShape& s, int32_t* radius
                        (const FrameDesc*)a.table, (const int32_t*)a.prefix, radius, sc, csplit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "adjoint window kernel launch");
-    hipLaunchKernelGGL((fov_adj_sum_kernel<T, GV, ARGS>), dim3(a.nfrag), dim3(kThreads), 0, stream, a, s,
+    const auto ks = fov_adj_sum_kernel<T, GV, ARGS>;
+    const size_t sum_lds = (size_t)kSumCh * s.bmax * (s.bmax + 1) * sizeof(T);
+    if (sum_lds + 64 > lds_limit) return set_error(FOV_ERANGE, "adjoint output tile does not fit in LDS");
+    if ((st = allow_dyn_lds((const void*)ks, lds_limit)) != FOV_OK) return st;
+    hipLaunchKernelGGL(ks, dim3(a.nfrag), dim3(kThreads), sum_lds, stream, a, s,
                        (const FrameDesc*)a.table, (const int32_t*)a.prefix, (const int32_t*)radius, (const T*)sc);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "adjoint sum kernel launch");
@@ -460,6 +537,7 @@ AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax) {
     s.pitch_b = inter_pitch(bmax + 2 * s.pad_b, es);
     s.tap_stride = round_up(2 * r_cap + 1 + kAdjWeightLead + 8, 4);
     s.tap_elems = (16 / es) * s.tap_stride;
+    s.bdiv = bmax > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)bmax - 1) / (uint64_t)bmax) : 0u;
     // window rows transposed per run: the whole window when the LDS stays within kAdjLdsBudget,
     // else as many rows (a multiple of 4, at least 4) as fit beside the staged gradient
     const size_t g = ((size_t)s.tap_elems + (size_t)bmax * s.pitch_b) * es, row = (size_t)s.pitch_a * es;
