@@ -11,7 +11,7 @@ namespace fov {
 struct AdjShape {
     int32_t bmax;     // largest fragment side
     int32_t sw;       // columns of a transposed window in scratch: bmax + 2 r_cap
-    int32_t sh;       // column stride of a window in scratch: bmax + 2 r_cap rounded up to 4
+    int32_t sh;       // column stride of a window in scratch (a multiple of 128 bytes)
     int32_t cmax;     // largest channel count
     int32_t pitch_a;  // LDS row pitch of the vertical transpose's rows (zero columns around the data)
     int32_t pad_b;    // zero rows above a staged gradient column
@@ -29,6 +29,10 @@ constexpr size_t kAdjLdsBudget = (size_t)96 << 10;
 // start up to three taps early (to keep 16-byte LDS loads aligned) and read
 // zeros there.
 constexpr int kAdjWeightLead = 4;
+
+// Rows before a fragment's first row in its window columns: r rounded up to
+// 128 bytes of elements of size es.
+__host__ __device__ inline int window_lead(int r, int es) { return round_up(r, 128 / es); }
 
 AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax);
 // Dynamic LDS of the window kernel.

@@ -14,20 +14,23 @@
 // cdf_b(-p-1) = sum_{i <= -p-1} w_b(i) for input p, and output L-1 the extra
 // weight cdf_b(p-L).
 //
-// Two kernels after the plan kernel (radius and taps of every fragment):
-//  1. fov_adj_window_kernel — one workgroup per fragment computes its whole
-//     transposed window, channel by channel, as the forward computes a
-//     fragment: the gradient is staged in LDS (column-major, zero rows
-//     around it), the vertical transpose writes the window's rows into a
-//     second LDS buffer (zero columns around the data), and the horizontal
-//     transpose writes the folded window to scratch, column by column (lanes
-//     take rows, so the stores of a wave cover consecutive addresses).
+// Two kernels:
+//  1. fov_adj_window_kernel — one workgroup per fragment and channel: the
+//     fragment's sigma, radius and normalised taps (kept in LDS), then its
+//     transposed window as the forward computes a fragment: the gradient is
+//     staged in LDS (column-major, zero rows around it), the vertical
+//     transpose writes the window's rows into a second LDS buffer (zero
+//     columns around the data), and the horizontal transpose writes the
+//     folded window to scratch, column by column (lanes take rows, so the
+//     stores of a wave cover consecutive addresses).  It also records each
+//     fragment's radius.
 //  2. fov_adj_sum_kernel — one workgroup per output tile (the fragment grid)
 //     adds up the windows of every fragment that reaches it, in a fixed
-//     order: no LDS, no barriers.
-// Both transposes are the forward's register-window correlations with the
-// taps read as scalar operands, run over the band of taps that meet the
-// fragment.
+//     order (lanes test the candidate fragments, a ballot lists the hits),
+//     reading window columns with buffer loads, and stores the tile along
+//     rows through an LDS transpose.
+// Both transposes are the forward's register-window correlations, run over
+// the band of taps that meet the fragment.
 #include "adjoint.h"
 
 #include <hip/hip_runtime.h>
@@ -55,9 +58,6 @@ __device__ __forceinline__ Window window_of(const Frag& F, int r, int h, int w) 
     v.x1 = min(F.xa + F.bw - 1 + r, w - 1);
     return v;
 }
-
-// Sum kernel: neighbours' radii read from radius[] (written by the window kernel), else recomputed.
-constexpr bool kSumLoadsRadius = true;
 
 // x / d for a launch constant d (0 <= x, x * d < 2^32): m = ceil(2^32 / d), 0 for d = 1.
 __device__ __forceinline__ int div_by(int x, uint32_t m) { return m ? (int)__umulhi((uint32_t)x, m) : x; }
@@ -103,8 +103,10 @@ __device__ __forceinline__ const T* taps_from(const T* taps, int stride, int t) 
     return static_cast<const T*>(__builtin_assume_aligned(taps + k * stride + kAdjWeightLead + k + t, 16));
 }
 
-// Transposed window of fragment gid into scratch[gid][c][x - x0][y - y0] (column-major, column
-// stride s.sh) for the frame columns x0..x1 and rows y0..y1-1 of its folded window.  Workgroup
+// Transposed window of fragment gid into scratch[gid][c][x - x0][y - ya + window_lead(r)]
+// (column-major, column stride s.sh) for the frame columns x0..x1 and rows y0..y1-1 of its folded
+// window: the fragment's own rows start on a 128-byte boundary, and so do those of the tiles above
+// and below when the block size is a multiple of 128 bytes of elements.  Workgroup
 // q takes fragment q / csplit and its channel share q % csplit (csplit workgroups per fragment).
 // GV: gradient values a thread holds per channel (bh * bw <= 256 GV).
 template <typename T, int GV, bool ARGS>
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
     const double sigma = fragment_sigma(fp, F.lb, F.bx, F.by);
     const int r = min(radius_of(sigma), a.r_cap);
     const int N = 2 * r + 1;
-    if (kSumLoadsRadius && share == 0 && tid == 0) radius[gid] = r;
+    if (share == 0 && tid == 0) radius[gid] = r;  // for the sum kernel
     const double inv = r > 0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
     double part = 0.0, mine = 0.0;
     for (int j = tid; j < N; j += kThreads) {
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void fov_adj_window_kernel(const FwdLaunc
         // Horizontal transpose Fold_x H^T of the window rows into scratch: lanes take rows, a wave
         // shares one group of 8 output columns, so the taps that meet the fragment form one
         // wave-uniform range.
-        T* dstc = dst0 + (size_t)c * s.sw * s.sh + (cr0 - win.y0);
+        T* dstc = dst0 + (size_t)c * s.sw * s.sh + (cr0 - F.ya + window_lead(r, (int)sizeof(T)));
         for (int ch = 0; ch * 64 < rows; ++ch)
         for (int gi = wave; gi < G8; gi += kThreads / 64) {
             const int X = win.x0 + gi * kPH;
@@ -318,7 +320,8 @@ constexpr int sum_batch() {
 }
 
 struct SumNb {
-    int b;  // fragment
+    int b;      // fragment
+    int ybase;  // frame row of the first element of its window columns
     Window w;
 };
 
@@ -347,7 +350,8 @@ __device__ __forceinline__ void load_window(T (&v)[kSumCh][PIX], const SumNb& n,
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
         const uint32_t dx = (uint32_t)(px[k] - n.w.x0), dy = (uint32_t)(py[k] - n.w.y0);
-        voff[k] = (dx <= wx && dy < wy) ? (dx * (uint32_t)s.sh + dy) * (uint32_t)sizeof(T) : kOutside;
+        voff[k] = (dx <= wx && dy < wy) ? (dx * (uint32_t)s.sh + (uint32_t)(py[k] - n.ybase)) * (uint32_t)sizeof(T)
+                                        : kOutside;
     }
     const int plane = s.sw * s.sh;
 #pragma unroll
@@ -411,20 +415,21 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
             // Candidates j0 .. j0 + 63 (row-major over the fragments within reach), one per lane: the
             // ballot of those whose window meets the tile lists them in the fixed summation order.
             const int j = j0 + lane;
-            int b = 0, y0 = 0, y1 = 0, x0 = 0, x1 = 0;
+            int b = 0, y0 = 0, y1 = 0, x0 = 0, x1 = 0, yb = 0;
             bool hit = false;
             if (j < ncand) {
                 const int jy = (int)(((float)j + 0.5f) * rnx);
                 const int by = by_lo + jy, bx = bx_lo + (j - jy * nx);
                 const int lb = by * nbx + bx;
                 b = first + lb;
-                const int rb = kSumLoadsRadius ? radius[b] : min(radius_of(fragment_sigma(fp, lb, bx, by)), a.r_cap);
+                const int rb = radius[b];
                 // its folded window (as window_of gives it for that fragment)
                 const int X0 = fp.origin_x + bx * B, Y0 = fp.origin_y + by * B;
                 x0 = max(X0 - rb, 0);
                 x1 = min(X0 + B - 1 + rb, d.w - 1);
                 y0 = max(Y0 - rb, 0);
                 y1 = min(Y0 + B + rb, d.h);
+                yb = max(Y0, 0) - window_lead(rb, (int)sizeof(T));
                 hit = x1 >= Q.xa && x0 < Q.xa + Q.bw && y1 > Q.ya && y0 < Q.ya + Q.bh;
             }
             uint64_t m = __ballot(hit);
@@ -438,6 +443,7 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
                         const int l = __builtin_ctzll(m);
                         m &= m - 1;
                         nb[q].b = lane_value(b, l);
+                        nb[q].ybase = lane_value(yb, l);
                         nb[q].w.y0 = lane_value(y0, l);
                         nb[q].w.y1 = lane_value(y1, l);
                         nb[q].w.x0 = lane_value(x0, l);
@@ -483,16 +489,14 @@ __global__ __launch_bounds__(kThreads) void fov_adj_sum_kernel(const FwdLaunch a
     }
 }
 
-// One window workgroup per fragment and channel (else per fragment).
-constexpr bool kWindowSplit = true;
-
 template <typename T, int GV, bool ARGS>
 fov_status launch_kernels(const FwdLaunch& a, const AdjShape& s, int32_t* radius, T* sc, hipStream_t stream,
                           size_t lds_limit) {
     const auto kw = fov_adj_window_kernel<T, GV, ARGS>;
     fov_status st;
     if ((st = allow_dyn_lds((const void*)kw, lds_limit)) != FOV_OK) return st;
-    const int csplit = kWindowSplit && (int64_t)a.nfrag * s.cmax * kThreads < ((int64_t)1 << 32) ? s.cmax : 1;
+    // one window workgroup per fragment and channel (per fragment if the grid would be too large)
+    const int csplit = (int64_t)a.nfrag * s.cmax * kThreads < ((int64_t)1 << 32) ? s.cmax : 1;
     hipLaunchKernelGGL(kw, dim3(a.nfrag * csplit), dim3(kThreads), adjoint_lds(s, sizeof(T)), stream, a, s,
                        (const FrameDesc*)a.table, (const int32_t*)a.prefix, radius, sc, csplit);
     hipError_t e = hipGetLastError();
@@ -528,7 +532,7 @@ AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax) {
     AdjShape s;
     s.bmax = bmax;
     s.sw = bmax + 2 * r_cap;
-    s.sh = round_up(bmax + 2 * r_cap, 4);
+    s.sh = round_up(bmax + r_cap + window_lead(r_cap, es), 128 / es);
     s.cmax = cmax;
     s.pitch_a = tile_pitch(bmax + kPadA + 7, es);
     // rows one wave's tasks span in the vertical transpose, minus one
