@@ -59,9 +59,6 @@ __device__ __forceinline__ Window window_of(const Frag& F, int r, int h, int w) 
     return v;
 }
 
-// x / d for a launch constant d (0 <= x, x * d < 2^32): m = ceil(2^32 / d), 0 for d = 1.
-__device__ __forceinline__ int div_by(int x, uint32_t m) { return m ? (int)__umulhi((uint32_t)x, m) : x; }
-
 // Frame buffers as global-memory pointers (pointers read from the frame table would otherwise be
 // accessed with flat instructions).
 template <typename T>
@@ -541,7 +538,7 @@ AdjShape adjoint_shape(int es, int r_cap, int bmax, int cmax) {
     s.pitch_b = inter_pitch(bmax + 2 * s.pad_b, es);
     s.tap_stride = round_up(2 * r_cap + 1 + kAdjWeightLead + 8, 4);
     s.tap_elems = (16 / es) * s.tap_stride;
-    s.bdiv = bmax > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)bmax - 1) / (uint64_t)bmax) : 0u;
+    s.bdiv = div_magic((uint32_t)bmax);
     // window rows transposed per run: the whole window when the LDS stays within kAdjLdsBudget,
     // else as many rows (a multiple of 4, at least 4) as fit beside the staged gradient
     const size_t g = ((size_t)s.tap_elems + (size_t)bmax * s.pitch_b) * es, row = (size_t)s.pitch_a * es;

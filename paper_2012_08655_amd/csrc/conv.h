@@ -286,6 +286,13 @@ __device__ __forceinline__ void vconv(TC (&acc)[kPV], const TC* col, int N, cons
     vstep_part(left, acc, B, A, w + j0);
 }
 
+// Division by a value d >= 1 fixed for a launch or work item: div_magic(d) = ceil(2^32 / d) (0 for
+// d = 1), and x / d = div_by(x, div_magic(d)) for 0 <= x with x * d < 2^32 (the multiplier's excess
+// over 2^32 / d is below 1, so it moves x / d by less than x * d / 2^32 < 1 of 1/d).
+__host__ __device__ inline uint32_t div_magic(uint32_t d) { return d > 1 ? 0xFFFFFFFFu / d + 1u : 0u; }
+
+__device__ __forceinline__ int div_by(int x, uint32_t m) { return m ? (int)__umulhi((uint32_t)x, m) : x; }
+
 // ---- fragments of a launch ---------------------------------------------------------------------
 // Last frame whose first fragment is <= gid (prefix has nframes+1 entries).
 __device__ __forceinline__ int frame_search(const int32_t* __restrict__ prefix, int nframes, int gid) {
