@@ -120,3 +120,17 @@ def test_adjoint_largest_and_odd_blocks_f64(fov, orc, dev, B):
     got = fov.backward(torch.from_numpy(g).to(dev), p, layout="CHW").cpu().numpy()
     ref = orc.adjoint(g, p)
     assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_adjoint_frame_table_big_blocks_f64(fov, orc, dev):
+    # more frames than travel in the kernel arguments (the kernels read the uploaded frame table)
+    # with 64 px fragments (four values per thread, window rows transposed in runs)
+    rng = np.random.default_rng(31)
+    n, c, h, w = 17, 2, 70, 90
+    ps = [synth.params_dict(rng.uniform(0, w - 1), rng.uniform(0, h - 1), 5.0, 0.2, 16.0, 64,
+                            -int(rng.integers(0, 64)), -int(rng.integers(0, 64))) for _ in range(n)]
+    g = rng.random((n, c, h, w))
+    got = fov.backward(torch.from_numpy(g).to(dev), ps).cpu().numpy()
+    for i in range(n):
+        ref = orc.adjoint(g[i], ps[i])
+        assert np.max(np.abs(got[i] - ref)) <= 1e-12 * max(1.0, np.abs(ref).max()), i
