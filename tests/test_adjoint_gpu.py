@@ -134,3 +134,18 @@ def test_adjoint_frame_table_big_blocks_f64(fov, orc, dev):
     for i in range(n):
         ref = orc.adjoint(g[i], ps[i])
         assert np.max(np.abs(got[i] - ref)) <= 1e-12 * max(1.0, np.abs(ref).max()), i
+
+
+def test_adjoint_sigma_map_f64(fov, orc, dev):
+    # per-fragment sigma from a map (values below 0, NaN and above the cap included), f64
+    rng = np.random.default_rng(14)
+    h, w, B = 90, 130, 16
+    p = synth.params_dict(0, 0, 0, 0, 9.0, B, -5, -11)
+    nby, nbx = orc.grid(h, w, p)
+    smap = rng.uniform(-1, 11, size=(nby, nbx)).astype(np.float32)
+    smap[0, 0] = np.nan
+    pd = dict(p, sigma_map=torch.from_numpy(smap.reshape(-1)).to(dev))
+    g = rng.random((2, h, w))
+    got = fov.backward(torch.from_numpy(g).to(dev), pd, layout="CHW").cpu().numpy()
+    ref = orc.adjoint(g, p, sigma_map=smap.astype(np.float64))
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
