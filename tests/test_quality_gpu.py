@@ -41,9 +41,10 @@ def study(fov, orc, dev):
     summary = {"%d%s" % (B, "_shift" if s else ""): {"mean": round(v[0], 5), "min_of_average_map": round(v[1], 5)}
                for (B, s), v in sorted(out.items())}
     print("quality", json.dumps(summary))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "quality_ssim.json"), "w") as f:
-        json.dump({"frames": NFRAMES, "size": [H, W], "params": base, "ssim": summary}, f, indent=1)
+    dest = os.environ.get("FOV_QUALITY_JSON")  # optional copy of the study's numbers
+    if dest:
+        with open(dest, "w") as f:
+            json.dump({"frames": NFRAMES, "size": [H, W], "params": base, "ssim": summary}, f, indent=1)
     return out
 
 
