@@ -151,13 +151,22 @@ __device__ __forceinline__ void hconv(TC (&acc)[kPH], const TS* row, int N, cons
     hstep_part(left, acc, C, A, B, w + j0);
 }
 
-// ---- symmetric horizontal pass for 8-bit input staged as fp16 ----------------------------------
+// ---- symmetric horizontal pass for 8-bit input staged as 16-bit integers ----------------------
 // The taps are symmetric (w_{-k} = w_k), so out[p] = w_0 x[p] + sum_k w_k (x[p-k] + x[p+k]).  The
-// staged values are integers 0..255 in fp16, so a packed fp16 add forms two such pair sums exactly
-// (at most 510), and one v_fma_mix_f32 per output and distance multiplies a sum by the FP32 weight:
-// 4.5 adds and 8 FMAs per distance for 8 outputs instead of 16 FMAs.  Two samples of a 32-bit
-// register are the outputs (2q, 2q+1) at even distances and (2q-1, 2q) at odd ones; with the
-// centre of output 0 on a 4-sample boundary every operand is a whole register.
+// staged values are integers 0..255, two per 32-bit register, so one 32-bit integer add forms two
+// such pair sums exactly (at most 510: no carry crosses into the upper half), and one
+// v_fma_mix_f32 per output and distance multiplies a sum by the FP32 weight.  The mixed FMA reads
+// a 16-bit sum s as the fp16 subnormal s * 2^-24, and the weights it gets are scaled by 2^24
+// (kSymScale), so it forms the exact product w_k * s as with an unscaled weight and an fp16 s.
+// 4.5 adds and 8 FMAs per distance for 8 outputs instead of 16 FMAs; the integer add is a VALU
+// form that the hardware can issue beside another wave's instruction in the same cycle.  Two
+// samples of a 32-bit register are the outputs (2q, 2q+1) at even distances and (2q-1, 2q) at odd
+// ones; with the centre of output 0 on a 4-sample boundary every operand is a whole register.  At
+// odd distances the outer registers use one half only: the lower halves there are staged samples
+// (the tile starts (-r) mod 4 columns left of the padded tile, so the sample left of output 0's
+// window at an odd r is staged), and whatever the upper half of the last one holds, a carry out
+// of it is dropped.
+constexpr float kSymScale = 16777216.0f;  // 2^24
 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ h2v as_h2(uint32_t u) { return __builtin_bit_cast(h2v, u); }
@@ -171,14 +180,14 @@ __device__ __forceinline__ void sym_tap(float (&acc)[kPH], const uint32_t* l, co
     if constexpr (ODD) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const h2v s = as_h2(l[q]) + as_h2(t[q]);
+            const h2v s = as_h2(l[q] + t[q]);
             if (q > 0) acc[2 * q - 1] = fmaf(wk, (float)s.x, acc[2 * q - 1]);
             if (q < 4) acc[2 * q] = fmaf(wk, (float)s.y, acc[2 * q]);
         }
     } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const h2v s = as_h2(l[q]) + as_h2(t[q]);
+            const h2v s = as_h2(l[q] + t[q]);
             acc[2 * q] = fmaf(wk, (float)s.x, acc[2 * q]);
             acc[2 * q + 1] = fmaf(wk, (float)s.y, acc[2 * q + 1]);
         }
@@ -206,7 +215,7 @@ __device__ __forceinline__ void sym_part(int nt, float (&acc)[kPH], uint2 L0, ui
 }
 
 // 8 horizontal outputs, radius r >= 1.  rc points at the centre of output 0 (8-byte aligned);
-// w0 = w_0 and ws[j] = w_{j+1} for j = 0..r-1 (16-byte aligned).  Reads samples rc[-r-3 .. r+10]:
+// w0 = 2^24 w_0 and ws[j] = 2^24 w_{j+1} for j = 0..r-1 (16-byte aligned).  Reads samples rc[-r-3 .. r+10]:
 // the ones outside [-r, r+7] fall in halves whose sums no output uses.  Sums are taken in the
 // order k = 0, 1, .., r.
 __device__ __forceinline__ void hconv_sym(float (&acc)[kPH], const _Float16* rc, int r, float w0,

@@ -14,16 +14,16 @@
 //
 //  3. fov_fwd_kernel — one workgroup per work item (Alg. 1): the padded
 //     tile (fragment plus r on each side, clamp-to-edge) is staged into LDS
-//     with row-coalesced loads, 8-bit input kept exact as fp16; a horizontal
+//     with row-coalesced loads, 8-bit input as 16-bit integers; a horizontal
 //     pass writes the fp32 intermediate into LDS; a vertical pass produces the
 //     fragment (Appendix "Workload of the Block", "Shared Memory").  Each
 //     thread computes 8 (horizontal) or 4 (vertical) outputs and slides the
 //     filter window through registers (the register reuse of Appendix "Data
-//     Reuse"); the weights are read with scalar loads and used as SGPR
-//     operands of the FMAs.  For 8-bit input the horizontal pass adds the
-//     two samples that share a weight (the taps are symmetric) exactly in
-//     packed fp16 before the FP32 multiply-add.  A fragment with r = 0 is
-//     copied.
+//     Reuse"); the work item copies its weights to LDS and both passes read
+//     them as broadcast LDS loads.  For 8-bit input the horizontal pass adds
+//     the two samples that share a weight (the taps are symmetric) exactly,
+//     two sums per 32-bit integer add, before the FP32 multiply-add.  A
+//     fragment with r = 0 is copied.
 //
 // Every output sums its taps in the same order (k = -r .. r; for 8-bit input
 // the horizontal pass goes k = 0, then the pairs +-1 .. +-r) whatever the
@@ -148,10 +148,10 @@ struct Stager {
     }
 };
 
-// 8-bit input staged as exact fp16, two columns per lane and one 32-bit LDS
-// write per pair: the bytes b0, b1 are placed under the fp16 exponent of 1024
-// (bits 0x6400 | b encode 1024 + b exactly) and 1024 is subtracted from both
-// halves at once.  One 128-column chunk is prefetched.  Bytes are read with
+// 8-bit input staged as 16-bit integers, two columns per lane and one 32-bit
+// LDS write per pair (b1 << 16 | b0).  Read as fp16, such a half is the
+// subnormal b * 2^-24, which the symmetric horizontal pass multiplies by taps
+// scaled by 2^24.  One 128-column chunk is prefetched.  Bytes are read with
 // buffer loads over the frame (a descriptor covering its bytes): each lane's
 // two column offsets are fixed for the fragment and a row's offset is a
 // wave-uniform scalar, so no per-row address arithmetic runs on the vector
@@ -159,9 +159,7 @@ struct Stager {
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ half2_t bytes_to_half2(uint32_t b0, uint32_t b1) {
-    const half2_t bias = {(_Float16)1024.0f, (_Float16)1024.0f};
-    const uint32_t bits = (b1 << 16) | b0 | 0x64006400u;
-    return __builtin_bit_cast(half2_t, bits) - bias;
+    return __builtin_bit_cast(half2_t, (b1 << 16) | b0);
 }
 
 // Raw buffer descriptor (dword 3 as gfx9 expects for untyped access).
@@ -313,7 +311,8 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
     const int IP = inter_pitch(g.TH, sizeof(TC));
     // The fragment's taps are copied to LDS once (read by the passes as broadcast LDS loads, so
     // the inner loops wait on LDS only): w[0 .. N-1] = w_{-r} .. w_r, then for the symmetric
-    // pass ws[j] = w_{j+1} (j = 0 .. r-1) at a 16-byte boundary.
+    // pass ws[j] = 2^24 w_{j+1} (j = 0 .. r-1) at a 16-byte boundary (scaled for the 16-bit
+    // integer samples, which it reads as fp16 subnormals; the scaling is exact).
     TC* w = reinterpret_cast<TC*>(smem + kTileLead);
     TC* ws = w + round_up(g.N, 4);
     TS* tile = reinterpret_cast<TS*>(smem + kTileLead + tap_lds_bytes(a.r_cap, sizeof(TC)));
@@ -324,7 +323,7 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
         for (int i = tid; i < g.N; i += kThreads) {
             const TC v = wg[i];
             w[i] = v;
-            if (kSym && i > r) ws[i - r - 1] = v;
+            if (kSym && i > r) ws[i - r - 1] = v * kSymScale;
         }
     }
     const TIn* in = static_cast<const TIn*>(d.in);
@@ -354,7 +353,7 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
             TC acc[kPH];
 #pragma unroll
             for (int p = 0; p < kPH; ++p) acc[p] = 0;
-            if constexpr (kSym) hconv_sym(acc, tile + ty * TP + x0 + r + sh, r, w[r], ws);
+            if constexpr (kSym) hconv_sym(acc, tile + ty * TP + x0 + r + sh, r, w[r] * kSymScale, ws);
             else hconv(acc, tile + ty * TP + x0, g.N, w);
             TC* dst = inter + x0 * IP + s0 + ty;
 #pragma unroll
