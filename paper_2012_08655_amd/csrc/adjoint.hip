@@ -59,16 +59,6 @@ __device__ __forceinline__ Window window_of(const Frag& F, int r, int h, int w) 
     return v;
 }
 
-// Frame buffers as global-memory pointers (pointers read from the frame table would otherwise be
-// accessed with flat instructions).
-template <typename T>
-using global_ptr = __attribute__((address_space(1))) T*;
-
-template <typename T>
-__device__ __forceinline__ global_ptr<T> as_global(T* p) {
-    return (global_ptr<T>)p;
-}
-
 // Blur strength of fragment (bx, by), local index lb, of a frame: from the sigma map or from the
 // midpoint's eccentricity (Sec. 2).
 __device__ __forceinline__ double fragment_sigma(const FrameParams& fp, int lb, int bx, int by) {

@@ -52,6 +52,23 @@ __host__ __device__ inline size_t tap_lds_bytes(int r_cap, int ec) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Smallest s with 2^s >= v (v >= 1).
+__host__ __device__ inline int ceil_log2(int v) {
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return s;
+}
+
+// Frame buffers as global-memory pointers (pointers read from the frame table would otherwise be
+// accessed with flat instructions).
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(T* p) {
+    return (global_ptr<T>)p;
+}
+
 // Index of the calling wavefront in its workgroup, as a scalar (uniform) value.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 

@@ -327,58 +327,76 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
         }
     }
     const TIn* in = static_cast<const TIn*>(d.in);
-    TOut* out = static_cast<TOut*>(d.out);
     const int nst = (g.TH + SR - 1) / SR;
     const int nunits = (c_hi - c_lo) * nst;  // (channel, strip) units, channels c_lo .. c_hi - 1
+    // Tasks map to (row, column group) and (column, row group) with shifts: the column groups of a
+    // 16-row block and the columns of the vertical pass are padded to powers of two (the padding
+    // tasks idle; 32-pixel fragments have none).  LDS offsets stay below 2^24, so their products
+    // are 24-bit multiplies.
+    const int gsh = ceil_log2(g.G), xsh = ceil_log2(F.bw);
+    const uint32_t IPH = (uint32_t)IP * kPH;
     Stager<TIn, TS> st;
     const int64_t span = (int64_t)(d.c - 1) * d.isc + (int64_t)(d.h - 1) * d.ish + (int64_t)(d.w - 1) * d.isw + 1;
     st.setup(F.xa - r - sh, TW, d.w, d.isw, d.ish, d.h, in, (uint32_t)span);
     st.issue(in + c_lo * d.isc, F.ya - r, SR);
     st.commit(tile, TP);
     __syncthreads();
+    int cu = 0, sidx = 0;  // the current unit: channel c_lo + cu, strip sidx
     for (int u = 0; u < nunits; ++u) {
-        const int cu = u / nst, sidx = u - cu * nst, c = c_lo + cu;
+        const int c = c_lo + cu;
         const int s0 = sidx * SR, rows = min(SR, g.TH - s0);
-        if (u + 1 < nunits) {
-            const int cn = (u + 1) / nst, sn = (u + 1) - cn * nst;
-            st.issue(in + (c_lo + cn) * d.isc, F.ya - r + sn * SR, min(SR, g.TH - sn * SR));
+        int cn = cu, sn = sidx + 1;  // the next unit
+        if (sn == nst) {
+            sn = 0;
+            ++cn;
         }
+        if (u + 1 < nunits) st.issue(in + (c_lo + cn) * d.isc, F.ya - r + sn * SR, min(SR, g.TH - sn * SR));
         // Horizontal pass.  Task t: lanes of a 16-lane group take 16
         // consecutive rows of one column group (conflict-free row reads).
-        const int ntask = round_up(rows, 16) * g.G;
+        const int ntask = round_up(rows, 16) << gsh;
         for (int t = tid; t < ntask; t += kThreads) {
-            const int blk = t >> 4, gi = blk % g.G;
-            const int ty = ((blk / g.G) << 4) | (t & 15), x0 = gi * kPH;
-            if (ty >= rows) continue;
+            const int blk = t >> 4, gi = blk & ((1 << gsh) - 1);
+            const int ty = ((blk >> gsh) << 4) | (t & 15);
+            if (ty >= rows || gi >= g.G) continue;
             TC acc[kPH];
 #pragma unroll
             for (int p = 0; p < kPH; ++p) acc[p] = 0;
-            if constexpr (kSym) hconv_sym(acc, tile + ty * TP + x0 + r + sh, r, w[r] * kSymScale, ws);
-            else hconv(acc, tile + ty * TP + x0, g.N, w);
-            TC* dst = inter + x0 * IP + s0 + ty;
+            const TS* row = tile + __umul24((uint32_t)ty, (uint32_t)TP) + gi * kPH;
+            if constexpr (kSym) hconv_sym(acc, row + r + sh, r, w[r] * kSymScale, ws);
+            else hconv(acc, row, g.N, w);
+            TC* dst = inter + __umul24((uint32_t)gi, IPH) + s0 + ty;
 #pragma unroll
             for (int p = 0; p < kPH; ++p) dst[p * IP] = acc[p];
         }
         __syncthreads();  // the tile is free; the channel's intermediate may be complete
         if (sidx == nst - 1) {
-            // Vertical pass over the complete intermediate of channel c.
-            TOut* oc = out + c * d.osc;
-            for (int t = tid; t < F.bw * g.GV; t += kThreads) {
-                const int gv = t / F.bw, x = t - gv * F.bw, y0 = gv * kPV;
+            // Vertical pass over the complete intermediate of channel c.  Output rows step by the
+            // row stride from one 64-bit address per task.
+            const int64_t osh = d.osh, osw = d.osw;
+            const global_ptr<TOut> oc =
+                as_global(static_cast<TOut*>(d.out)) + c * d.osc + (int64_t)F.ya * osh + (int64_t)F.xa * osw;
+            const int ntv = g.GV << xsh;
+            for (int t = tid; t < ntv; t += kThreads) {
+                const int x = t & ((1 << xsh) - 1), y0 = (t >> xsh) * kPV;
+                if (x >= F.bw) continue;
                 TC acc[kPV];
 #pragma unroll
                 for (int p = 0; p < kPV; ++p) acc[p] = 0;
-                vconv(acc, inter + x * IP + y0, g.N, w);
-                TOut* o = oc + (int64_t)(F.xa + x) * d.osw;
+                vconv(acc, inter + __umul24((uint32_t)x, (uint32_t)IP) + y0, g.N, w);
+                global_ptr<TOut> o = oc + (int64_t)x * osw + (int64_t)y0 * osh;
 #pragma unroll
-                for (int p = 0; p < kPV; ++p)
-                    if (y0 + p < F.bh) o[(int64_t)(F.ya + y0 + p) * d.osh] = to_out<TOut, TC>(acc[p]);
+                for (int p = 0; p < kPV; ++p) {
+                    if (y0 + p < F.bh) *o = to_out<TOut, TC>(acc[p]);
+                    o += osh;
+                }
             }
         }
         if (u + 1 < nunits) {
             st.commit(tile, TP);
             __syncthreads();  // next strip staged; every thread is past the previous vertical pass
         }
+        cu = cn;
+        sidx = sn;
     }
 }
 
