@@ -71,7 +71,7 @@ __device__ __forceinline__ TOut to_out(TC v) { return (TOut)v; }
 template <>
 __device__ __forceinline__ uint8_t to_out<uint8_t, float>(float v) {
     v = rintf(v);  // round half to even
-    v = fminf(fmaxf(v, 0.0f), 255.0f);
+    v = __builtin_amdgcn_fmed3f(v, 0.0f, 255.0f);  // clamp to [0, 255] (the value is never NaN)
     return (uint8_t)v;
 }
 
@@ -384,10 +384,18 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
                 for (int p = 0; p < kPV; ++p) acc[p] = 0;
                 vconv(acc, inter + __umul24((uint32_t)x, (uint32_t)IP) + y0, g.N, w);
                 global_ptr<TOut> o = oc + (int64_t)x * osw + (int64_t)y0 * osh;
+                if ((F.bh & (kPV - 1)) == 0) {  // whole row groups (uniform): no per-row test
 #pragma unroll
-                for (int p = 0; p < kPV; ++p) {
-                    if (y0 + p < F.bh) *o = to_out<TOut, TC>(acc[p]);
-                    o += osh;
+                    for (int p = 0; p < kPV; ++p) {
+                        *o = to_out<TOut, TC>(acc[p]);
+                        o += osh;
+                    }
+                } else {
+#pragma unroll
+                    for (int p = 0; p < kPV; ++p) {
+                        if (y0 + p < F.bh) *o = to_out<TOut, TC>(acc[p]);
+                        o += osh;
+                    }
                 }
             }
         }
