@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "foveated Mpix/s (1080p RGB) + p99 frame latency, served vs plain launch"
 PROFILE_EVERY = 4  # main-kernel timing samples one call in four of the timed region
 H, W, C = 1080, 1920, 3
-PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector, published (two VALU instructions per SIMD and cycle)
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector, published (two wave64 FMA instructions issued per SIMD every four cycles)
 HBM_PEAK_GBS = 8000.0
 
 
