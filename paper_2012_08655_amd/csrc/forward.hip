@@ -460,6 +460,7 @@ __global__ __launch_bounds__(kThreads) void fov_fwd_kernel(const FwdLaunch a, co
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderMaxRings = 1024;
 constexpr int kOrderCells = 12288;
+constexpr int kOrderHeld = 4096;  // items whose (key, radius word) the order kernel holds in LDS
 constexpr int kOrderBins = 16;  // angle bins per ring: one 16-lane segment of a wave scans a ring
 constexpr int kXcds = 8;
 
@@ -573,7 +574,8 @@ __global__ __launch_bounds__(64) void fov_plan_weights_kernel(const FwdLaunch a,
 // (one per channel).
 // One workgroup: LDS histogram over (ring, angle bin), scans, scatter; the
 // order inside one (ring, angle bin) cell is arbitrary and results do not
-// depend on it.
+// depend on it.  Up to kOrderHeld items keep their key and radius word in LDS
+// from the histogram pass to the scatter, so memory is read once.
 
 __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t* __restrict__ okey,
                                                                   const int32_t* __restrict__ radius, int n_arg,
@@ -588,14 +590,17 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
     __shared__ int ring_base[kOrderMaxRings]; // first slot of each ring (multiple of 8)
     __shared__ int chan_base[kOrderMaxRings]; // split rings: first slot of each after the queue
     __shared__ int total_slots, total_extra;
+    __shared__ int2 held[kOrderHeld];         // (key, radius word) per item when n <= kOrderHeld
     // rings whose fragments (r <= cs_rmax) are split by channel: ring >= small0
     const int small0 = (cs_rmax >= 0 && cmax > 1) ? max(nrings - 1 - cs_rmax, 0) : nrings;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ncell = nrings * nang;
     for (int i = tid; i < ncell; i += kOrderThreads) cells[i] = 0;
     __syncthreads();
+    const bool hold = n <= kOrderHeld;
     for (int i = tid; i < n; i += kOrderThreads) {
         const int key = okey[i >> (2 * L)];
+        if (hold) held[i] = make_int2(key, radius[i >> (2 * L)]);
         if (key >= 0) atomicAdd(&cells[key], 1);  // -1: the lower fragment of a merged pair
     }
     __syncthreads();
@@ -648,9 +653,10 @@ __global__ __launch_bounds__(kOrderThreads) void fov_order_kernel(const int32_t*
     __syncthreads();
     int2* ord = reinterpret_cast<int2*>(order);
     for (int i = tid; i < n; i += kOrderThreads) {
-        const int key = okey[i >> (2 * L)];
+        const int2 kr = hold ? held[i] : make_int2(okey[i >> (2 * L)], radius[i >> (2 * L)]);
+        const int key = kr.x;
         if (key < 0) continue;
-        const int rr = radius[i >> (2 * L)];
+        const int rr = kr.y;
         const int ring = key / nang;
         const int j = atomicAdd(&cells[key], 1);  // rank in the ring
         const int m = ring_n[ring];
