@@ -134,6 +134,28 @@ def test_cfg2_full_size_sampled(fov, orc, dev, fix):
     assert np.array_equal(y8.cpu().numpy(), np.clip(np.rint(yf.cpu().numpy()), 0, 255).astype(np.uint8))
 
 
+@pytest.mark.parametrize("h", [2048, 2080])
+def test_queue_item_count_around_the_held_key_limit(fov, orc, dev, h):
+    # The order kernel keeps each work item's key and radius word in LDS between its two passes
+    # for up to 4096 items and reads them from memory twice beyond that.  2048x2048 in 32 px
+    # fragments is exactly 4096 items, 2080x2048 is 4160; both against the oracle (u8 -> f32
+    # within 2e-5 on [0,1], u8 out within 1 LSB and equal to the rounded f32 output).
+    fr = synth.grating_frame(h, 2048, 1, seed=h)
+    rng = np.random.default_rng(h)
+    p = synth.params_cfg2(rng, h=h, w=2048)
+    t = torch.from_numpy(fr).to(dev)
+    y8 = fov.forward(t, p, layout="HWC")
+    yf = fov.forward(t, p, layout="HWC", out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    ys, xs = sample_points(rng, h, 2048, 32, 1000)
+    ref = orc.forward_points(fr.transpose(2, 0, 1).astype(np.float64), p, ys, xs)
+    got_f = yf.cpu().numpy()[ys, xs, :]
+    assert np.max(np.abs(got_f - ref)) <= TOL_F32 * 255
+    got8 = y8.cpu().numpy()[ys, xs, :].astype(np.int32)
+    assert np.max(np.abs(got8 - orc.to_u8(ref).astype(np.int32))) <= 1
+    assert np.array_equal(y8.cpu().numpy(), np.clip(np.rint(yf.cpu().numpy()), 0, 255).astype(np.uint8))
+
+
 @pytest.mark.parametrize("fix", ["centre", "rand0"])
 def test_cfg2_full_frame(fov, orc, dev, fix):
     # Every pixel of a 1920x1080 RGB u8 frame (32 px fragments, sigma = 0.02 (e - 64) capped
