@@ -280,6 +280,71 @@ __device__ __forceinline__ void hconv_sym(float (&acc)[kPH], const _Float16* rc,
     sym_part(NT, acc, LA, LB, LC, RC, RA, RB, ws + 4 * m);
 }
 
+// 4 horizontal outputs, the same pass for strips of few rows: a 16-row block of 8-output tasks
+// fills one wave, so a strip of one or two blocks would leave waves idle; with 4-output tasks
+// twice as many lanes share it.  The pairs are outputs (0, 1), (2, 3) at even distances and
+// (-1, 0), (1, 2), (3, 4) at odd ones, each output takes the same pair sums and FMAs in the same
+// order as in hconv_sym (bitwise the same results), and its reads (rc[-r-3 .. r+6]) stay
+// within those of the 8-output task whose columns it shares.
+template <bool ODD>
+__device__ __forceinline__ void sym_tap4(float (&acc)[4], const uint32_t* l, const uint32_t* t, float wk) {
+    if constexpr (ODD) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const h2v s = as_h2(l[q] + t[q]);
+            if (q > 0) acc[2 * q - 1] = fmaf(wk, (float)s.x, acc[2 * q - 1]);
+            if (q < 2) acc[2 * q] = fmaf(wk, (float)s.y, acc[2 * q]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const h2v s = as_h2(l[q] + t[q]);
+            acc[2 * q] = fmaf(wk, (float)s.x, acc[2 * q]);
+            acc[2 * q + 1] = fmaf(wk, (float)s.y, acc[2 * q + 1]);
+        }
+    }
+}
+
+// Distances 4m+1 .. 4m+NT: L0 < L1 hold samples c-4m-4 .. c-4m+3, R0 < R1 samples c+4m .. c+4m+7.
+template <int NT>
+__device__ __forceinline__ void sym_block4(float (&acc)[4], uint2 L0, uint2 L1, uint2 R0, uint2 R1,
+                                           const float* __restrict__ wk) {
+    const uint32_t l[4] = {L0.x, L0.y, L1.x, L1.y};
+    const uint32_t t[4] = {R0.x, R0.y, R1.x, R1.y};
+    if (NT >= 1) sym_tap4<true>(acc, l + 1, t, wk[0]);
+    if (NT >= 2) sym_tap4<false>(acc, l + 1, t + 1, wk[1]);
+    if (NT >= 3) sym_tap4<true>(acc, l, t + 1, wk[2]);
+    if (NT >= 4) sym_tap4<false>(acc, l, t + 2, wk[3]);
+}
+
+// rc, w0 and ws as for hconv_sym.
+__device__ __forceinline__ void hconv_sym4(float (&acc)[4], const _Float16* rc, int r, float w0,
+                                           const float* __restrict__ ws) {
+    uint2 Lc = load_grp(rc), Rc = Lc;  // the block's inner groups: c-4m and c+4m
+    {
+        const uint32_t x[2] = {Lc.x, Lc.y};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            acc[2 * q] = fmaf(w0, (float)as_h2(x[q]).x, acc[2 * q]);
+            acc[2 * q + 1] = fmaf(w0, (float)as_h2(x[q]).y, acc[2 * q + 1]);
+        }
+    }
+    const int M = r >> 2, NT = r & 3;
+    for (int m = 0; m < M; ++m) {
+        const uint2 L0 = load_grp(rc - 4 * (m + 1));
+        const uint2 R1 = load_grp(rc + 4 * (m + 1));
+        sym_block4<4>(acc, L0, Lc, Rc, R1, ws + 4 * m);
+        Lc = L0;
+        Rc = R1;
+    }
+    if (NT == 0) return;
+    const uint2 L0 = load_grp(rc - 4 * (M + 1));
+    const uint2 R1 = load_grp(rc + 4 * (M + 1));
+    if (NT == 1) sym_block4<1>(acc, L0, Lc, Rc, R1, ws + 4 * M);
+    else if (NT == 2) sym_block4<2>(acc, L0, Lc, Rc, R1, ws + 4 * M);
+    else sym_block4<3>(acc, L0, Lc, Rc, R1, ws + 4 * M);
+}
+
 template <typename TC>
 __device__ __forceinline__ void vstep_part(int nt, TC (&acc)[kPV], const TC (&X)[4], const TC (&Y)[4],
                                            const TC* __restrict__ w) {

@@ -354,7 +354,25 @@ __device__ __forceinline__ void process_fragment(const FwdLaunch& a, int gid, in
         // Horizontal pass.  Task t: lanes of a 16-lane group take 16
         // consecutive rows of one column group (conflict-free row reads).
         const int ntask = round_up(rows, 16) << gsh;
-        for (int t = tid; t < ntask; t += kThreads) {
+        bool four = false;  // 8-bit strips of at most half a workgroup of tasks: 4-output tasks
+        if constexpr (kSym) {
+            if (ntask <= kThreads / 2) {
+                four = true;
+                for (int t = tid; t < 2 * ntask; t += kThreads) {
+                    const int blk = t >> 4, gi = blk & ((2 << gsh) - 1);
+                    const int ty = ((blk >> (gsh + 1)) << 4) | (t & 15);
+                    if (ty >= rows || gi >= 2 * g.G) continue;
+                    float a4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    const TS* row = tile + __umul24((uint32_t)ty, (uint32_t)TP) + gi * 4;
+                    hconv_sym4(a4, row + r + sh, r, w[r] * kSymScale, ws);
+                    TC* dst = inter + __umul24((uint32_t)gi, (uint32_t)(4 * IP)) + s0 + ty;
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) dst[p * IP] = a4[p];
+                }
+            }
+        }
+        const int ntask8 = four ? 0 : ntask;
+        for (int t = tid; t < ntask8; t += kThreads) {
             const int blk = t >> 4, gi = blk & ((1 << gsh) - 1);
             const int ty = ((blk >> gsh) << 4) | (t & 15);
             if (ty >= rows || gi >= g.G) continue;
