@@ -12,6 +12,9 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
+# (split, strip rows, persistent, merge, channel split).  With 16- and 32-row strips every 8-bit
+# strip is one or two 16-row blocks, so its horizontal pass runs as 4-output tasks; with 64-row
+# strips most run as 8-output tasks: the bitwise comparison covers both forms.
 CONFIGS = [cfg for cfg in itertools.product((1, 2, 4), (16, 32, 64), (0, 1), (0, 1), (0, 1))
            if not ((cfg[3] or cfg[4]) and cfg[0] != 1)]
 
